@@ -1,0 +1,178 @@
+"""TEST INFRASTRUCTURE ONLY: Python face of the FP64 CPU oracle.
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  It loads ``liboracle.so`` (built from ``oracle.cpp`` and
+``oracle_mac.cpp`` by ``oracle/build_oracle.py``) and never touches the HIP
+library under test.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build_oracle
+            build_oracle.build()
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.orc_direct.argtypes = [_f32p, _f32p, C.c_int64, C.c_float, vp, C.c_int64, _f64p, vp]
+        L.orc_tree_build.restype = vp
+        L.orc_tree_build.argtypes = [_f32p, _f32p, C.c_int64, C.c_int, C.c_int]
+        L.orc_tree_free.argtypes = [vp]
+        L.orc_tree_sizes.argtypes = [vp, _i64p]
+        L.orc_tree_export.argtypes = [vp] + [vp] * 8
+        L.orc_mac_open.argtypes = [_f32p, _f32p, _f32p, C.c_float]
+        for f in (L.orc_lists, L.orc_lists_brute):
+            f.argtypes = [vp, C.c_float, vp, vp, vp, vp, vp, vp]
+        L.orc_forces.argtypes = [vp, C.c_float, C.c_float, vp, C.c_int64, _f64p, vp]
+        L.orc_counts.argtypes = [vp, C.c_float, _i64p]
+        L.orc_diagnostics.argtypes = [_f32p, _f64p, vp, C.c_int64, _f64p]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _pos(pos):
+    return np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def direct(pos, mass, eps, targets=None):
+    """FP64 direct summation; returns (acc [nt,3], pot [nt]) for the targets."""
+    pos = _pos(pos)
+    mass = np.ascontiguousarray(mass, dtype=np.float32)
+    n = pos.shape[0]
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else tg.shape[0]
+    acc = np.zeros((nt, 3))
+    pot = np.zeros(nt)
+    rc = lib().orc_direct(pos, mass, n, float(eps), _ptr(tg), nt, acc, _ptr(pot))
+    assert rc == 0
+    return acc, pot
+
+
+def mac_open(gmin, gmax, geo, theta) -> bool:
+    return bool(lib().orc_mac_open(np.asarray(gmin, np.float32), np.asarray(gmax, np.float32),
+                                   np.asarray(geo, np.float32), float(theta)))
+
+
+class Tree:
+    """The oracle's own octree (independent builder), with its FP64 moments."""
+
+    def __init__(self, pos, mass, n_leaf=16, n_group=64):
+        self.pos = _pos(pos)
+        self.mass = np.ascontiguousarray(mass, dtype=np.float32)
+        self.n = self.pos.shape[0]
+        h = lib().orc_tree_build(self.pos, self.mass, self.n, int(n_leaf), int(n_group))
+        if not h:
+            raise ValueError("oracle tree build rejected its arguments")
+        self._h = C.c_void_p(h)
+        s = np.zeros(5, np.int64)
+        lib().orc_tree_sizes(self._h, s)
+        self.n_cells, self.n_leaves, self.n_groups, self.max_depth = (int(v) for v in s[1:])
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.orc_tree_free(self._h)
+            self._h = None
+
+    def export(self):
+        nc, ng = self.n_cells, self.n_groups
+        out = dict(order=np.zeros(self.n, np.int32), topo=np.zeros((nc, 4), np.int32),
+                   geo=np.zeros((nc, 4), np.float32), mp=np.zeros((nc, 10)),
+                   box=np.zeros((nc, 6)), depth=np.zeros(nc, np.int32),
+                   groups=np.zeros(ng, np.int32), cube=np.zeros(4))
+        lib().orc_tree_export(self._h, *(_ptr(out[k]) for k in
+                                         ("order", "topo", "geo", "mp", "box", "depth", "groups",
+                                          "cube")))
+        return out
+
+    def _lists(self, fn, theta):
+        nc, nl = C.c_int64(), C.c_int64()
+        fn(self._h, float(theta), None, None, None, None, C.byref(nc), C.byref(nl))
+        c_off = np.zeros(self.n_groups + 1, np.int64)
+        l_off = np.zeros(self.n_groups + 1, np.int64)
+        c_ids = np.zeros(max(1, nc.value), np.int32)
+        l_ids = np.zeros(max(1, nl.value), np.int32)
+        fn(self._h, float(theta), _ptr(c_off), _ptr(c_ids), _ptr(l_off), _ptr(l_ids),
+           C.byref(nc), C.byref(nl))
+        return c_off, c_ids[:nc.value], l_off, l_ids[:nl.value]
+
+    def lists(self, theta):
+        """(c_off, c_ids, l_off, l_ids): CSR lists per group from the stack walk."""
+        return self._lists(lib().orc_lists, theta)
+
+    def lists_brute(self, theta):
+        """The same lists from their walk-free characterisation (slow)."""
+        return self._lists(lib().orc_lists_brute, theta)
+
+    def counts(self, theta):
+        """[n_groups, 3]: |C_g|, |L_g|, source particles in L_g."""
+        out = np.zeros((self.n_groups, 3), np.int64)
+        lib().orc_counts(self._h, float(theta), out)
+        return out
+
+    def forces(self, theta, eps, groups=None):
+        """FP64 same-tree forces; (acc [n,3], pot [n]) by input index.  With
+        `groups`, only those groups' particles are filled (others are NaN)."""
+        acc = np.full((self.n, 3), np.nan)
+        pot = np.full(self.n, np.nan)
+        sel = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
+        rc = lib().orc_forces(self._h, float(theta), float(eps), _ptr(sel),
+                              0 if sel is None else sel.shape[0], acc, _ptr(pot))
+        assert rc == 0
+        return acc, pot
+
+
+def diagnostics(mass, acc, pot):
+    """FP64 (sum m a [3], 1/2 sum m phi)."""
+    mass = np.ascontiguousarray(mass, dtype=np.float32)
+    acc = np.ascontiguousarray(acc, dtype=np.float64)
+    p = None if pot is None else np.ascontiguousarray(pot, dtype=np.float64)
+    out = np.zeros(4)
+    lib().orc_diagnostics(mass, acc, _ptr(p), mass.shape[0], out)
+    return out[:3], out[3]
+
+
+def rel_err(a, a_ref):
+    """Per-particle relative error |a - a_ref| / |a_ref| (Sec. 3.1)."""
+    a = np.asarray(a, np.float64)
+    a_ref = np.asarray(a_ref, np.float64)
+    if a.ndim == 2:
+        return np.linalg.norm(a - a_ref, axis=1) / np.linalg.norm(a_ref, axis=1)
+    return np.abs(a - a_ref) / np.abs(a_ref)
+
+
+def percentile_nr(x, q):
+    """Nearest-rank percentile: the ceil(q*n)-th smallest value (q in (0,1])."""
+    x = np.sort(np.asarray(x).ravel())
+    k = max(1, int(np.ceil(q * x.size - 1e-12)))
+    return float(x[k - 1])
+
+
+def err_summary(a, a_ref):
+    e = rel_err(a, a_ref)
+    return dict(p50=percentile_nr(e, 0.5), p90=percentile_nr(e, 0.9),
+                p99=percentile_nr(e, 0.99), max=float(e.max()))
