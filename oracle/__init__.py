@@ -36,6 +36,9 @@ def lib():
         L.orc_tree_free.argtypes = [vp]
         L.orc_tree_sizes.argtypes = [vp, _i64p]
         L.orc_tree_export.argtypes = [vp] + [vp] * 8
+        L.orc_tree_cubes.argtypes = [vp, _f64p]
+        L.orc_multipole_eval.argtypes = [_f32p, _f32p, C.c_int64, _f64p, C.c_float, C.c_int,
+                                         _f64p]
         L.orc_mac_open.argtypes = [_f32p, _f32p, _f32p, C.c_float]
         for f in (L.orc_lists, L.orc_lists_brute):
             f.argtypes = [vp, C.c_float, vp, vp, vp, vp, vp, vp]
@@ -73,6 +76,15 @@ def direct(pos, mass, eps, targets=None):
     return acc, pot
 
 
+def multipole_eval(pos, mass, target, eps, use_quad=True):
+    """Field of a particle set's monopole(+quadrupole) at `target`: (acc[3], phi)."""
+    out = np.zeros(4)
+    lib().orc_multipole_eval(_pos(pos), np.ascontiguousarray(mass, dtype=np.float32),
+                             _pos(pos).shape[0], np.asarray(target, np.float64), float(eps),
+                             int(bool(use_quad)), out)
+    return out[:3], out[3]
+
+
 def mac_open(gmin, gmax, geo, theta) -> bool:
     return bool(lib().orc_mac_open(np.asarray(gmin, np.float32), np.asarray(gmax, np.float32),
                                    np.asarray(geo, np.float32), float(theta)))
@@ -107,6 +119,12 @@ class Tree:
         lib().orc_tree_export(self._h, *(_ptr(out[k]) for k in
                                          ("order", "topo", "geo", "mp", "box", "depth", "groups",
                                           "cube")))
+        return out
+
+    def cubes(self):
+        """[n_cells, 4]: octree cube corner xyz and side of every cell."""
+        out = np.zeros((self.n_cells, 4))
+        lib().orc_tree_cubes(self._h, out)
         return out
 
     def _lists(self, fn, theta):

@@ -506,6 +506,57 @@ int orc_tree_export(const void* h, int32_t* order, int32_t* topo, float* geo, do
   return 0;
 }
 
+// Per-cell octree cube: corner xyz and side [nc x 4] (FP64).
+int orc_tree_cubes(const void* h, double* cubes) {
+  const Tree& t = *(const Tree*)h;
+  for (size_t c = 0; c < t.cells.size(); ++c) {
+    for (int k = 0; k < 3; ++k) cubes[4 * c + k] = t.cells[c].corner[k];
+    cubes[4 * c + 3] = t.cells[c].side;
+  }
+  return 0;
+}
+
+// Multipole (monopole + traceless quadrupole about the centre of mass) of an
+// arbitrary particle set, evaluated at one target point with the same
+// particle-cell formula the tree evaluation uses.  use_quad = 0 drops Q.
+// out = {ax, ay, az, phi}.
+int orc_multipole_eval(const float* pos, const float* mass, int64_t n, const double* target,
+                       float eps, int use_quad, double* out) {
+  Tree t;
+  t.n = n;
+  for (int k = 0; k < 3; ++k) t.x[k].resize(n);
+  t.m.resize(n);
+  t.order.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < 3; ++k) t.x[k][i] = (double)pos[3 * i + k];
+    t.m[i] = (double)mass[i];
+    t.order[i] = (int32_t)i;
+  }
+  Cell c;
+  c.first = 0;
+  c.n = n;
+  cell_properties(t, c);
+  if (!use_quad)
+    for (double& q : c.Q) q = 0;
+  t.cells.push_back(c);
+  // A one-particle "group" at the target sees this cell through the p-c path.
+  t.x[0].push_back(target[0]);
+  t.x[1].push_back(target[1]);
+  t.x[2].push_back(target[2]);
+  t.m.push_back(1.0);
+  t.order.push_back((int32_t)n);
+  Cell g;
+  g.first = n;
+  g.n = 1;
+  t.cells.push_back(g);
+  std::vector<int32_t> C{0}, Lv;
+  std::vector<double> acc(3 * (n + 1)), pot(n + 1);
+  eval_group(t, 1, C, Lv, (double)eps * (double)eps, acc.data(), pot.data());
+  for (int k = 0; k < 3; ++k) out[k] = acc[3 * n + k];
+  out[3] = pot[n];
+  return 0;
+}
+
 int orc_mac_open(const float* gmin, const float* gmax, const float* geo, float theta) {
   float th2 = theta * theta;
   return mac_open(gmin, gmax, geo, th2) ? 1 : 0;
