@@ -1,0 +1,160 @@
+"""Benchmark of the force path on one MI355X.
+
+A step is one force evaluation of the whole hot path: count walk, offsets,
+write walk, evaluation (p-c + p-p, compensated), unsort and the FP64
+diagnostics, on the 2^20-particle Plummer sphere (theta = 0.5, eps = 1e-3,
+n_leaf = 16, groups of <= 64) whose tree is already resident in HBM.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("particles/s and % FP32 VALU peak at N=2^20, learned vs θ-MAC at p99 err 1e-3")
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (spec sheet)
+FLOP_PP, FLOP_PC = 38, 70  # the paper's per-interaction convention (Sec. 3.3)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pos, m, w, gpu_acc, gpu_pot, n_groups_sample=1024):
+    """The oracle as it stands, on a bounded sample of the same workload:
+    its own tree build plus the same-tree walk and FP64 evaluation of a
+    seeded sample of groups, and the FP64 direct sum for 4096 sampled
+    particles (the tree-error reference)."""
+    import oracle
+    cores = oracle.num_threads()
+    t0 = time.perf_counter()
+    O = oracle.Tree(pos, m, w["n_leaf"], 64)
+    t_build = time.perf_counter() - t0
+    rng = np.random.default_rng(4096)
+    sel = np.sort(rng.choice(O.n_groups, min(n_groups_sample, O.n_groups), replace=False))
+    t0 = time.perf_counter()
+    ar, pr = O.forces(0.5, w["eps"], groups=sel)
+    t_eval = time.perf_counter() - t0
+    k = ~np.isnan(pr)
+    n_sample = int(k.sum())
+    ea = oracle.rel_err(gpu_acc[k], ar[k])
+    ep = oracle.rel_err(gpu_pot[k], pr[k])
+    tg = np.sort(rng.choice(pos.shape[0], 4096, replace=False))
+    t0 = time.perf_counter()
+    ad, _ = oracle.direct(pos, m, w["eps"], targets=tg)
+    t_direct = time.perf_counter() - t0
+    e_dir = oracle.rel_err(gpu_acc[tg], ad)
+    return {
+        "value": n_sample / t_eval, "unit": "particles/s", "cores": cores, "kind": "oracle",
+        "sample": (f"same-tree FP64 walk+evaluation of {len(sel)} seeded groups "
+                   f"({n_sample} particles) of the 2^20 Plummer tree at theta=0.5; "
+                   f"oracle tree build {t_build:.2f} s; FP64 direct sum of 4096 sampled "
+                   f"particles {t_direct:.2f} s"),
+        "eval_s": t_eval,
+        "gpu_vs_same_tree_oracle": {"acc_med": float(np.median(ea)), "acc_max": float(ea.max()),
+                                    "pot_med": float(np.median(ep)), "pot_max": float(ep.max())},
+        "gpu_vs_direct_fp64": oracle.err_summary(gpu_acc[tg], ad) | {"n": 4096},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plummer1m")
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1005_5384_amd import octgrav as og
+    from paper_1005_5384_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.WORKLOADS[args.workload]
+    log(f"bench: generating {args.workload} n={w['n']}")
+    pos, m = W.make(args.workload)
+    n = pos.shape[0]
+    t0 = time.perf_counter()
+    T = og.Tree(pos, m, w["n_leaf"], 64)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    log(f"bench: tree built+uploaded in {t_build:.3f} s: {T.stats}")
+    acc = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    pot = torch.empty(n, dtype=torch.float32, device="cuda")
+    theta, eps = args.theta, w["eps"]
+
+    for _ in range(args.warmup):
+        T.forces(theta, eps, acc=acc, pot=pot, timed=True)
+    torch.cuda.synchronize()
+    log("bench: warmup done")
+
+    phases = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        T.forces(theta, eps, acc=acc, pot=pot, timed=True)
+        phases.append(T.last_timings())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"bench: {args.steps} steps in {elapsed:.4f} s")
+
+    counts = T.last_counts()
+    flops = FLOP_PP * counts["n_pp"] + FLOP_PC * counts["n_pc"]
+    ph = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+    eval_s = ph["eval"] * 1e-3
+    achieved = flops / eval_s / 1e12
+    ms_step = elapsed / args.steps * 1e3
+    path_tflops = flops / (ms_step * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": n * args.steps / elapsed,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "distribution": w["gen"], "theta": theta,
+                   "eps": eps, "n_leaf": w["n_leaf"], "n_group": 64, "mac": "theta",
+                   "accumulation": "compensated"},
+        "roofline": {"bound": "alu", "kernel": "eval_kernel", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops, "flop_convention": "38 per p-p, 70 per p-c"},
+        "path_frac_peak": path_tflops / PEAK_FP32_TFLOPS,
+        "path_tflops": path_tflops,
+        "interactions_per_s": (counts["n_pp"] + counts["n_pc"]) / (ms_step * 1e-3),
+        "interactions": counts,
+        "phases_ms": ph,
+        "host_build_upload_s": t_build,
+        "tree": T.stats,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle) ...")
+        a = acc.double().cpu().numpy()
+        p = pot.double().cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(pos, m, w, a, p)
+        log("bench: cpu baseline done")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,162 @@
+/*
+ * octgrav.h -- C ABI of an MI355X (gfx950) implementation of the group
+ * tree-walk gravity method of E. Gaburov, J. Bedorf and S. Portegies Zwart,
+ * "Gravitational tree-code on graphics processing units: implementation in
+ * CUDA", ICCS 2010 (Procedia Computer Science).
+ *
+ * Split of the work (Sec. 2): the host builds the octree, the tight boxes,
+ * the boundary cubes and the multipole moments in FP64 (Sec. 2.1); the GPU
+ * walks the tree once per particle group to build a cell (node) interaction
+ * list and a leaf interaction list (Sec. 2.2, the tree-walk and test-cell
+ * listings), then evaluates softened particle-cell (monopole + quadrupole)
+ * and particle-particle interactions from those lists (Sec. 2.3, the
+ * body-node and body-leaf listings).  Interaction arithmetic is FP32 with
+ * compensated per-particle accumulation; FP64 on the GPU is used only for the
+ * momentum and energy diagnostics.  G = 1.
+ *
+ * Conventions shared by every call:
+ *   - Return codes: 0 = OK, negative = error (codes below).  Calls that
+ *     return a pointer return NULL on failure.  octgrav_last_error() gives
+ *     the calling thread's message for its last failure.  No C++ exception
+ *     crosses this boundary.
+ *   - Positions are row-major n x 3 FP32 [x0 y0 z0 x1 ...]; masses n FP32.
+ *     Outputs are always in the caller's original particle order.
+ *   - A handle must not be used by two threads at once.
+ *   - Device pointers are HIP device allocations on the current device (for
+ *     example torch tensors on cuda:0); host pointers are ordinary memory.
+ */
+#ifndef OCTGRAV_H
+#define OCTGRAV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OCTGRAV_OK 0
+#define OCTGRAV_EINVAL (-1)    /* bad argument (NULL, n < 1, theta outside [0,1], eps <= 0, ...) */
+#define OCTGRAV_ENOMEM (-2)    /* host or device allocation failed */
+#define OCTGRAV_EHIP (-3)      /* a HIP runtime call or kernel launch failed */
+#define OCTGRAV_ECAPACITY (-4) /* an internal capacity bound was exceeded after retry */
+
+/* octgrav_build_tree_ex flags */
+#define OCTGRAV_BUILD_HOST_ONLY 1u /* build and keep the host tree only: no device
+                                      memory, no HIP call; forces/lists return EINVAL */
+
+/* octgrav_forces_ex flags */
+#define OCTGRAV_PLAIN_SUM 1u /* plain FP32 accumulation instead of compensated */
+#define OCTGRAV_TIMED 2u     /* record HIP events around each kernel phase */
+
+typedef struct octgrav_tree octgrav_tree;
+
+typedef struct {
+  int64_t n;               /* particles */
+  int64_t n_cells;         /* cells (nodes + leaves), breadth-first numbered */
+  int64_t n_leaves;        /* leaves */
+  int64_t n_groups;        /* particle groups (walk units) */
+  int64_t max_depth;       /* deepest cell level (root = 0, at most 21) */
+  int64_t max_level_cells; /* most cells on one level */
+  int64_t n_work;          /* evaluation work items (groups split in chunks of 64) */
+  int64_t n_leaf, n_group; /* build parameters */
+} octgrav_stats;
+
+/* Host copies of the built tree; every pointer is caller-owned and may be NULL.
+ * Sizes come from octgrav_tree_stats. */
+typedef struct {
+  int32_t* perm;   /* [n]          sorted position -> caller's particle index */
+  int32_t* topo;   /* [n_cells*4]  first_child, n_child (0 = leaf), first particle, n particles */
+  float* geo;      /* [n_cells*4]  FP32 boundary centre xyz and side (opening-test input) */
+  float* mp;       /* [n_cells*12] FP32 com xyz, M | Qxx Qyy Qzz Qxy | Qxz Qyz 0 0 */
+  double* mp64;    /* [n_cells*10] FP64 M, com xyz, Qxx Qyy Qzz Qxy Qxz Qyz */
+  double* box;     /* [n_cells*6]  FP64 tight box min xyz, max xyz */
+  int32_t* depth;  /* [n_cells]    level of each cell */
+  int32_t* groups; /* [n_groups]   cell id of each group, ascending first particle */
+  double* cube;    /* [4]          root cube corner xyz and side */
+} octgrav_tree_view;
+
+/*
+ * Builds the tree of Sec. 2.1 on the host in FP64 and uploads it.
+ *   pos   host, n x 3 FP32, finite, |x| < 2^60 (keeps FP32 squared distances finite)
+ *   mass  host, n FP32, each > 0 and finite
+ *   n     1 <= n < 2^31
+ *   n_leaf  leaf capacity, 1..64: a cell is a leaf iff it holds n <= n_leaf
+ *           particles or sits at depth 21 (coincident particles).
+ * Groups are the maximal cells with at most 64 particles (Sec. 2.1).  The
+ * inputs are copied; the caller may free them when the call returns.  The
+ * handle owns all internal host and device memory until octgrav_free.
+ * Returns NULL on failure.
+ */
+octgrav_tree* octgrav_build_tree(const float* pos, const float* mass, int64_t n, int32_t n_leaf);
+
+/* As octgrav_build_tree with an explicit group capacity n_group (1..1024)
+ * and flags (OCTGRAV_BUILD_*). */
+octgrav_tree* octgrav_build_tree_ex(const float* pos, const float* mass, int64_t n,
+                                    int32_t n_leaf, int32_t n_group, uint32_t flags);
+
+/*
+ * Accelerations and potentials of every particle (Sec. 2.2 + 2.3):
+ * per-group walk with the opening angle theta, then evaluation of the cell
+ * list (softened monopole + traceless quadrupole) and the leaf list (softened
+ * particle-particle, self excluded from the potential).
+ *   theta  0 <= theta <= 1 (theta <= 1 guarantees that every cell containing a
+ *          group particle is opened, so no self term goes through a multipole)
+ *   eps    Plummer softening length, > 0
+ *   acc    device, n x 3 FP32, caller's order (written)
+ *   pot    device, n FP32, caller's order (written), or NULL
+ * Runs on the handle's stream and returns once the results are complete on it.
+ */
+int octgrav_forces(octgrav_tree* t, float theta, float eps, float* acc, float* pot);
+
+/* As octgrav_forces with OCTGRAV_PLAIN_SUM / OCTGRAV_TIMED flags. */
+int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float* pot,
+                      uint32_t flags);
+
+/* Releases the handle and everything it owns.  NULL is a no-op. */
+void octgrav_free(octgrav_tree* t);
+
+/* Message of the calling thread's last failure ("" if none).  The string
+ * stays valid until the thread's next octgrav call. */
+const char* octgrav_last_error(void);
+
+/* Sets the HIP stream (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream)
+ * that later calls on this handle run on.  NULL selects the null stream. */
+int octgrav_set_stream(octgrav_tree* t, void* hip_stream);
+
+/* Sizes of the built tree. */
+int octgrav_tree_stats(const octgrav_tree* t, octgrav_stats* s);
+
+/* Copies the host tree into caller-provided arrays (see octgrav_tree_view). */
+int octgrav_export_tree(const octgrav_tree* t, const octgrav_tree_view* v);
+
+/*
+ * Interaction lists of every group at opening angle theta, built by the GPU
+ * walk (Sec. 2.2: a count walk, offsets, a write walk) and copied to the host
+ * in CSR form over groups; ids are cell ids in ascending order.  Two-call
+ * pattern: with c_off/c_ids/l_off/l_ids NULL only *n_c and *n_l (total
+ * entries) are set; otherwise c_off and l_off hold n_groups+1 int64 each and
+ * c_ids/l_ids at least *n_c / *n_l int32 entries.
+ */
+int octgrav_lists(octgrav_tree* t, float theta, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
+                  int32_t* l_ids, int64_t* n_c, int64_t* n_l);
+
+/* FP64 diagnostics of the last octgrav_forces call, reduced on the GPU:
+ * mom = sum_i m_i a_i and *w = 1/2 sum_i m_i phi_i (0 if pot was NULL). */
+int octgrav_diagnostics(octgrav_tree* t, double mom[3], double* w);
+
+/* Interaction totals of the last forces/lists call: out[0] = cell-list
+ * entries, out[1] = leaf-list entries, out[2] = particle-cell interactions
+ * sum_g |g| |C_g|, out[3] = particle-particle interactions sum_g |g| n_src(L_g)
+ * (self pairs included, as they are evaluated). */
+int octgrav_last_counts(octgrav_tree* t, int64_t out[4]);
+
+/* Kernel-phase times in ms of the last OCTGRAV_TIMED forces call, measured
+ * with HIP events on the handle's stream: out[0] count walk, out[1] offsets,
+ * out[2] write walk, out[3] evaluation, out[4] diagnostics, out[5] total. */
+int octgrav_last_timings(octgrav_tree* t, double out[6]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCTGRAV_H */

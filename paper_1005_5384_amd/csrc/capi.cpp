@@ -1,0 +1,402 @@
+// C ABI of the library (declared in include/octgrav.h): argument checks,
+// ownership of host and device memory, and the order of the device phases
+// of one force call (Sec. 2: count walk, offsets, write walk, evaluation),
+// followed by the FP64 diagnostics.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "octgrav.h"
+#include "octgrav_internal.h"
+
+using namespace octgrav;
+
+namespace octgrav {
+int fallback_waves();
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+// Set by the environment variable OCTGRAV_FAIL_ALLOC=1 (test-only fault
+// injection): every device allocation of the library fails.
+bool alloc_fault() {
+  const char* v = std::getenv("OCTGRAV_FAIL_ALLOC");
+  return v && v[0] == '1';
+}
+
+// Set by OCTGRAV_LDS_QUEUE=<power of two> (test-only): shrinks the walk's
+// LDS frontier so that groups overflow into the global-memory fallback walk.
+int lds_queue_entries() {
+  const char* v = std::getenv("OCTGRAV_LDS_QUEUE");
+  int q = v ? std::atoi(v) : 2048;
+  if (q < 64 || q > 2048 || (q & (q - 1))) q = 2048;
+  return q;
+}
+
+}  // namespace
+
+struct octgrav_tree {
+  HostTree h;
+  bool dev = false;
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;
+  DevTree dt{};
+  WalkBufs wb{};
+  double* d_diag_part = nullptr;
+  double* d_diag = nullptr;
+  bool have_diag = false;
+  bool counts_valid = false;
+  hipEvent_t ev[6] = {};
+  double timings[6] = {0, 0, 0, 0, 0, 0};
+
+  ~octgrav_tree() {
+    for (void* p : allocs) hipFree(p);
+    for (hipEvent_t e : ev)
+      if (e) hipEventDestroy(e);
+  }
+
+  int dalloc(void** p, size_t bytes) {
+    if (alloc_fault()) return fail(OCTGRAV_ENOMEM, "device allocation failed (injected)");
+    if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(OCTGRAV_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    allocs.push_back(*p);
+    return OCTGRAV_OK;
+  }
+
+  void dfree(void* p) {
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) {
+      hipFree(p);
+      allocs.erase(it);
+    }
+  }
+
+  template <typename T>
+  int upload(const std::vector<T>& v, const T** out) {
+    void* p = nullptr;
+    if (int rc = dalloc(&p, v.size() * sizeof(T))) return rc;
+    if (!v.empty() && hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(OCTGRAV_EHIP, "hipMemcpy (tree upload) failed");
+    *out = (const T*)p;
+    return OCTGRAV_OK;
+  }
+
+  int to_device() {
+    const int64_t n = h.n, nc = h.n_cells(), ng = h.n_groups(), nw = (int64_t)h.work.size() / 2;
+    dt.n = n;
+    dt.nc = nc;
+    dt.ng = ng;
+    dt.nw = nw;
+    int rc;
+    if ((rc = upload(h.part, &dt.part)) || (rc = upload(h.perm, &dt.perm)) ||
+        (rc = upload(h.topo, &dt.topo)) || (rc = upload(h.geo, &dt.geo)) ||
+        (rc = upload(h.mp, &dt.mp)) || (rc = upload(h.ginfo, &dt.ginfo)) ||
+        (rc = upload(h.gbox, &dt.gbox)) || (rc = upload(h.work, &dt.work)))
+      return rc;
+    void* p;
+    if ((rc = dalloc(&p, (size_t)ng * 16))) return rc;
+    wb.cnt = (int32_t*)p;
+    if ((rc = dalloc(&p, (size_t)(ng + 1) * 8))) return rc;
+    wb.c_off = (int64_t*)p;
+    if ((rc = dalloc(&p, (size_t)(ng + 1) * 8))) return rc;
+    wb.l_off = (int64_t*)p;
+    if ((rc = dalloc(&p, 8 * 8))) return rc;
+    wb.tot = (int64_t*)p;
+    if ((rc = dalloc(&p, (size_t)scan_scratch_entries(ng) * 8))) return rc;
+    wb.blk = (int64_t*)p;
+    if ((rc = dalloc(&p, (size_t)ng * 4))) return rc;
+    wb.ovf_list = (int32_t*)p;
+    if ((rc = dalloc(&p, 4))) return rc;
+    wb.ovf_count = (int32_t*)p;
+    // Fallback frontier queues: a breadth-first FIFO never holds more than
+    // two consecutive levels, hence at most twice the widest level.
+    int64_t cap = 64;
+    while (cap < 2 * h.max_level_cells + 64) cap <<= 1;
+    wb.gq_cap = cap;
+    wb.gq_waves = fallback_waves();
+    while (wb.gq_waves > 8 && (int64_t)wb.gq_waves * cap * 4 > (int64_t(1) << 30)) wb.gq_waves >>= 1;
+    if ((rc = dalloc(&p, (size_t)wb.gq_waves * cap * 4))) return rc;
+    wb.gq = (int32_t*)p;
+    wb.lds_qcap = lds_queue_entries();
+    wb.cap_c = wb.cap_l = 0;
+    wb.c_ids = wb.l_ids = nullptr;
+    if ((rc = dalloc(&p, (size_t)diag_scratch_entries(n) * 8))) return rc;
+    d_diag_part = (double*)p;
+    if ((rc = dalloc(&p, 4 * 8))) return rc;
+    d_diag = (double*)p;
+    for (hipEvent_t& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) return fail(OCTGRAV_EHIP, "hipEventCreate failed");
+    dev = true;
+    return OCTGRAV_OK;
+  }
+
+  // Makes the list buffers hold at least (need_c, need_l) entries.
+  int reserve_lists(int64_t need_c, int64_t need_l) {
+    int rc;
+    void* p;
+    if (need_c > wb.cap_c) {
+      if (wb.c_ids) dfree(wb.c_ids);
+      wb.c_ids = nullptr;
+      wb.cap_c = 0;
+      int64_t cap = need_c + need_c / 8 + 1024;
+      if ((rc = dalloc(&p, (size_t)cap * 4))) return rc;
+      wb.c_ids = (int32_t*)p;
+      wb.cap_c = cap;
+    }
+    if (need_l > wb.cap_l) {
+      if (wb.l_ids) dfree(wb.l_ids);
+      wb.l_ids = nullptr;
+      wb.cap_l = 0;
+      int64_t cap = need_l + need_l / 8 + 1024;
+      if ((rc = dalloc(&p, (size_t)cap * 4))) return rc;
+      wb.l_ids = (int32_t*)p;
+      wb.cap_l = cap;
+    }
+    return OCTGRAV_OK;
+  }
+
+  int read_tot(int64_t* tot8) {
+    if (hipMemcpyAsync(tot8, wb.tot, 8 * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return fail(OCTGRAV_EHIP, std::string("device error: ") + hipGetErrorString(hipGetLastError()));
+    return OCTGRAV_OK;
+  }
+
+  // Count walk + offsets, then sizes the lists (a host read-back only when
+  // the current capacity might not suffice), then the write walk.
+  int lists_on_device(float theta, bool timed) {
+    if (timed) hipEventRecord(ev[0], stream);
+    if (launch_walk(dt, wb, theta, 0, stream)) return fail(OCTGRAV_EHIP, "count walk launch failed");
+    if (timed) hipEventRecord(ev[1], stream);
+    if (launch_scan(dt, wb, stream)) return fail(OCTGRAV_EHIP, "offsets launch failed");
+    if (timed) hipEventRecord(ev[2], stream);
+    if (wb.cap_c == 0) {
+      int64_t tot[8];
+      if (int rc = read_tot(tot)) return rc;
+      if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+      if (int rc = reserve_lists(tot[0], tot[1])) return rc;
+    }
+    if (launch_walk(dt, wb, theta, 1, stream)) return fail(OCTGRAV_EHIP, "write walk launch failed");
+    if (timed) hipEventRecord(ev[3], stream);
+    return OCTGRAV_OK;
+  }
+};
+
+extern "C" {
+
+const char* octgrav_last_error(void) { return g_err.c_str(); }
+
+octgrav_tree* octgrav_build_tree_ex(const float* pos, const float* mass, int64_t n, int32_t n_leaf,
+                                    int32_t n_group, uint32_t flags) {
+  g_err.clear();
+  try {
+    octgrav_tree* t = new octgrav_tree;
+    std::string err;
+    if (!build_host_tree(pos, mass, n, n_leaf, n_group, t->h, err)) {
+      delete t;
+      fail(OCTGRAV_EINVAL, err);
+      return nullptr;
+    }
+    if (!(flags & OCTGRAV_BUILD_HOST_ONLY)) {
+      if (t->to_device() != OCTGRAV_OK) {
+        std::string keep = g_err;
+        delete t;
+        g_err = keep;
+        return nullptr;
+      }
+    }
+    return t;
+  } catch (const std::bad_alloc&) {
+    fail(OCTGRAV_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    fail(OCTGRAV_EHIP, e.what());
+  }
+  return nullptr;
+}
+
+octgrav_tree* octgrav_build_tree(const float* pos, const float* mass, int64_t n, int32_t n_leaf) {
+  return octgrav_build_tree_ex(pos, mass, n, n_leaf, 64, 0);
+}
+
+void octgrav_free(octgrav_tree* t) { delete t; }
+
+int octgrav_set_stream(octgrav_tree* t, void* hip_stream) {
+  if (!t) return fail(OCTGRAV_EINVAL, "NULL handle");
+  t->stream = (hipStream_t)hip_stream;
+  return OCTGRAV_OK;
+}
+
+int octgrav_tree_stats(const octgrav_tree* t, octgrav_stats* s) {
+  if (!t || !s) return fail(OCTGRAV_EINVAL, "NULL argument");
+  const HostTree& h = t->h;
+  int64_t leaves = 0;
+  for (int64_t c = 0; c < h.n_cells(); ++c) leaves += h.topo[4 * c + 1] == 0;
+  s->n = h.n;
+  s->n_cells = h.n_cells();
+  s->n_leaves = leaves;
+  s->n_groups = h.n_groups();
+  s->max_depth = h.max_depth;
+  s->max_level_cells = h.max_level_cells;
+  s->n_work = (int64_t)h.work.size() / 2;
+  s->n_leaf = h.n_leaf;
+  s->n_group = h.n_group;
+  return OCTGRAV_OK;
+}
+
+int octgrav_export_tree(const octgrav_tree* t, const octgrav_tree_view* v) {
+  if (!t || !v) return fail(OCTGRAV_EINVAL, "NULL argument");
+  const HostTree& h = t->h;
+  auto cp = [](auto* dst, const auto& src) {
+    if (dst) std::memcpy(dst, src.data(), src.size() * sizeof(src[0]));
+  };
+  cp(v->perm, h.perm);
+  cp(v->topo, h.topo);
+  cp(v->geo, h.geo);
+  cp(v->mp, h.mp);
+  cp(v->mp64, h.mp64);
+  cp(v->box, h.box);
+  cp(v->depth, h.depth);
+  cp(v->groups, h.groups);
+  if (v->cube) {
+    for (int k = 0; k < 3; ++k) v->cube[k] = h.corner[k];
+    v->cube[3] = h.side;
+  }
+  return OCTGRAV_OK;
+}
+
+static int check_theta(const octgrav_tree* t, float theta) {
+  if (!t) return fail(OCTGRAV_EINVAL, "NULL handle");
+  if (!t->dev) return fail(OCTGRAV_EINVAL, "tree was built host-only");
+  if (!(theta >= 0.0f && theta <= 1.0f)) return fail(OCTGRAV_EINVAL, "theta must be in [0, 1]");
+  return OCTGRAV_OK;
+}
+
+int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float* pot,
+                      uint32_t flags) {
+  g_err.clear();
+  if (int rc = check_theta(t, theta)) return rc;
+  if (!(eps > 0.0f) || !std::isfinite(eps)) return fail(OCTGRAV_EINVAL, "eps must be finite and > 0");
+  if (!acc) return fail(OCTGRAV_EINVAL, "acc must be non-NULL");
+  try {
+    const bool timed = flags & OCTGRAV_TIMED, plain = flags & OCTGRAV_PLAIN_SUM;
+    t->counts_valid = false;
+    t->have_diag = false;
+    if (int rc = t->lists_on_device(theta, timed)) return rc;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      if (launch_eval(t->dt, t->wb, eps, plain, acc, pot, t->stream))
+        return fail(OCTGRAV_EHIP, "evaluation launch failed");
+      if (timed) hipEventRecord(t->ev[4], t->stream);
+      if (launch_diag(t->dt, acc, pot, t->d_diag_part, t->d_diag, t->stream))
+        return fail(OCTGRAV_EHIP, "diagnostics launch failed");
+      if (timed) hipEventRecord(t->ev[5], t->stream);
+      int64_t tot[8];
+      if (int rc = t->read_tot(tot)) return rc;
+      if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+      if (tot[0] <= t->wb.cap_c && tot[1] <= t->wb.cap_l) {
+        t->counts_valid = true;
+        t->have_diag = true;
+        if (timed) {
+          float ms;
+          for (int k = 0; k < 5; ++k) {
+            hipEventElapsedTime(&ms, t->ev[k], t->ev[k + 1]);
+            t->timings[k] = ms;
+          }
+          hipEventElapsedTime(&ms, t->ev[0], t->ev[5]);
+          t->timings[5] = ms;
+        }
+        return OCTGRAV_OK;
+      }
+      // Lists outgrew the buffers of an earlier call: grow and rewrite.
+      if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
+      if (timed) hipEventRecord(t->ev[2], t->stream);
+      if (launch_walk(t->dt, t->wb, theta, 1, t->stream))
+        return fail(OCTGRAV_EHIP, "write walk launch failed");
+      if (timed) hipEventRecord(t->ev[3], t->stream);
+    }
+    return fail(OCTGRAV_ECAPACITY, "list capacity still exceeded after retry");
+  } catch (const std::exception& e) {
+    return fail(OCTGRAV_EHIP, e.what());
+  }
+}
+
+int octgrav_forces(octgrav_tree* t, float theta, float eps, float* acc, float* pot) {
+  return octgrav_forces_ex(t, theta, eps, acc, pot, 0);
+}
+
+int octgrav_lists(octgrav_tree* t, float theta, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
+                  int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
+  g_err.clear();
+  if (int rc = check_theta(t, theta)) return rc;
+  if (!n_c || !n_l) return fail(OCTGRAV_EINVAL, "n_c and n_l must be non-NULL");
+  const bool want = c_off || c_ids || l_off || l_ids;
+  if (want && !(c_off && c_ids && l_off && l_ids))
+    return fail(OCTGRAV_EINVAL, "give all four list arrays or none");
+  try {
+    t->counts_valid = false;
+    int64_t tot[8];
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      if (int rc = t->lists_on_device(theta, false)) return rc;
+      if (int rc = t->read_tot(tot)) return rc;
+      if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+      if (tot[0] <= t->wb.cap_c && tot[1] <= t->wb.cap_l) break;
+      if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
+      if (attempt == 1) return fail(OCTGRAV_ECAPACITY, "list capacity exceeded");
+    }
+    t->counts_valid = true;
+    *n_c = tot[0];
+    *n_l = tot[1];
+    if (want) {
+      const int64_t ng = t->h.n_groups();
+      if (hipMemcpy(c_off, t->wb.c_off, (ng + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(l_off, t->wb.l_off, (ng + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          (tot[0] && hipMemcpy(c_ids, t->wb.c_ids, tot[0] * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+          (tot[1] && hipMemcpy(l_ids, t->wb.l_ids, tot[1] * 4, hipMemcpyDeviceToHost) != hipSuccess))
+        return fail(OCTGRAV_EHIP, "list copy-back failed");
+    }
+    return OCTGRAV_OK;
+  } catch (const std::exception& e) {
+    return fail(OCTGRAV_EHIP, e.what());
+  }
+}
+
+int octgrav_diagnostics(octgrav_tree* t, double mom[3], double* w) {
+  if (!t || !mom || !w) return fail(OCTGRAV_EINVAL, "NULL argument");
+  if (!t->have_diag) return fail(OCTGRAV_EINVAL, "no completed forces call on this handle");
+  double out[4];
+  if (hipMemcpy(out, t->d_diag, 32, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "diagnostics copy-back failed");
+  for (int k = 0; k < 3; ++k) mom[k] = out[k];
+  *w = out[3];
+  return OCTGRAV_OK;
+}
+
+int octgrav_last_counts(octgrav_tree* t, int64_t out[4]) {
+  if (!t || !out) return fail(OCTGRAV_EINVAL, "NULL argument");
+  if (!t->counts_valid) return fail(OCTGRAV_EINVAL, "no completed forces/lists call");
+  int64_t tot[8];
+  if (int rc = t->read_tot(tot)) return rc;
+  for (int k = 0; k < 4; ++k) out[k] = tot[k];
+  return OCTGRAV_OK;
+}
+
+int octgrav_last_timings(octgrav_tree* t, double out[6]) {
+  if (!t || !out) return fail(OCTGRAV_EINVAL, "NULL argument");
+  for (int k = 0; k < 6; ++k) out[k] = t->timings[k];
+  return OCTGRAV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations shared by the library's host and device sources.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace octgrav {
+
+constexpr int kMaxDepth = 21;   // levels below the root cube (63-bit Morton keys)
+constexpr int kChunk = 64;      // targets per evaluation work item
+
+// Host tree (Sec. 2.1), FP64 geometry and moments, FP32 device images.
+struct HostTree {
+  int64_t n = 0;
+  int n_leaf = 0, n_group = 0;
+  double corner[3] = {0, 0, 0}, side = 1;   // root cube
+  int max_depth = 0;
+  int64_t max_level_cells = 0;
+  std::vector<int32_t> perm;     // [n] sorted position -> input index
+  std::vector<float> part;       // [n*4] sorted x, y, z, m
+  std::vector<int32_t> topo;     // [nc*4] first_child, n_child, first, n
+  std::vector<int32_t> depth;    // [nc]
+  std::vector<double> box;       // [nc*6] tight box
+  std::vector<double> mp64;      // [nc*10] M, com, Q (xx yy zz xy xz yz)
+  std::vector<float> geo;        // [nc*4] f32 boundary centre, side
+  std::vector<float> mp;         // [nc*12] f32 com, M | Qxx Qyy Qzz Qxy | Qxz Qyz 0 0
+  std::vector<int32_t> groups;   // [ng] cell id
+  std::vector<int32_t> ginfo;    // [ng*4] first, n, cell, 0
+  std::vector<float> gbox;       // [ng*8] gmin xyz 0, gmax xyz 0
+  std::vector<int32_t> work;     // [nw*2] group, first target offset within group
+  int64_t n_cells() const { return (int64_t)depth.size(); }
+  int64_t n_groups() const { return (int64_t)groups.size(); }
+};
+
+// Builds the host tree; returns false with a message on bad input.
+bool build_host_tree(const float* pos, const float* mass, int64_t n, int n_leaf, int n_group,
+                     HostTree& out, std::string& err);
+
+// ------------------------------------------------------------------ device
+struct DevTree {
+  const float* part;     // float4 [n]
+  const int32_t* perm;   // [n]
+  const int32_t* topo;   // int4 [nc]
+  const float* geo;      // float4 [nc]
+  const float* mp;       // float4 x3 [nc]
+  const int32_t* ginfo;  // int4 [ng]
+  const float* gbox;     // float4 x2 [ng]
+  const int32_t* work;   // int2 [nw]
+  int64_t n, nc, ng, nw;
+};
+
+struct WalkBufs {
+  int32_t* cnt;        // int4 [ng]: |C|, |L|, n_src(L), frontier-overflow flag
+  int64_t* c_off;      // [ng+1]
+  int64_t* l_off;      // [ng+1]
+  int32_t* c_ids;      // [cap_c]
+  int32_t* l_ids;      // [cap_l]
+  int64_t cap_c, cap_l;
+  int64_t* tot;        // [8]: n_c, n_l, N_pc, N_pp, capacity-overflow, fallback-overflow
+  int64_t* blk;        // scan scratch: 2 per scan block
+  int32_t* ovf_list;   // [ng] groups whose LDS frontier overflowed
+  int32_t* ovf_count;  // [1]
+  int32_t* gq;         // global frontier queues for the fallback walk
+  int64_t gq_cap;      // entries per queue (power of two)
+  int32_t gq_waves;    // queues (waves) of the fallback walk
+  int32_t lds_qcap;    // LDS frontier entries used per wave (power of two <= 2048)
+};
+
+// Kernel launchers (device sources).  mode 0 = count, 1 = write.
+int launch_walk(const DevTree& T, const WalkBufs& B, float theta, int mode, void* stream);
+int launch_scan(const DevTree& T, const WalkBufs& B, void* stream);
+int launch_eval(const DevTree& T, const WalkBufs& B, float eps, bool plain, float* acc,
+                float* pot, void* stream);
+int launch_diag(const DevTree& T, const float* acc, const float* pot, double* part_sums,
+                double* out4, void* stream);
+int64_t scan_scratch_entries(int64_t ng);
+int64_t diag_scratch_entries(int64_t n);
+
+}  // namespace octgrav

@@ -1,0 +1,290 @@
+// Group tree walk (Sec. 2.2) for gfx950: builds each group's cell list and
+// leaf list under the opening angle theta, and the list offsets.
+//
+// The paper walks with one thread per group and a per-thread stack (the
+// tree-walk and test-cell listings).  Here one 64-lane wavefront walks one
+// group breadth-first: the frontier is a FIFO of candidate cells in LDS, the
+// 64 lanes test 64 candidates at once, and ballots compact the results.
+// Because cells are numbered breadth-first with contiguous children, a FIFO
+// walk meets candidates in ascending id order, so both lists come out in
+// canonical ascending order without a sort.
+//
+// Two walks as in the paper: a count walk (list sizes), device-side offsets
+// (the paper does this prefix sum on the host), then a write walk.  A group
+// whose frontier outgrows the LDS queue is flagged by the count walk and
+// handled by a fallback walk whose queues live in global memory and are
+// sized from the widest tree level, so they cannot overflow.
+#include <hip/hip_runtime.h>
+
+#include "octgrav_internal.h"
+
+namespace octgrav {
+namespace {
+
+constexpr int kQueueLds = 2048;  // LDS frontier entries per wave (power of two)
+constexpr int kFallbackWaves = 128;
+
+__device__ __forceinline__ int rank_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous (Morton-ordered, hence spatially coherent) range of groups so
+// that neighbouring groups share the XCD's L2.
+__device__ __forceinline__ int64_t xcd_slab(int64_t b, int64_t nblocks, int64_t n) {
+  int64_t per = nblocks >> 3;
+  int64_t i = (b & 7) * per + (b >> 3);
+  return i < n ? i : -1;
+}
+
+// Opening test (Sec. 2.2): open iff d2 == 0 or d2 * theta^2 < l^2, where d is
+// the distance from the cell's boundary centre to the group's tight box.
+// FP32, this exact operation order, no contraction: the decision is bit-exact
+// against any IEEE implementation of the same expression.
+__device__ __forceinline__ bool open_cell(float4 gmin, float4 gmax, float4 c, float th2) {
+#pragma clang fp contract(off)
+  float tx = fmaxf(fmaxf(gmin.x - c.x, c.x - gmax.x), 0.0f);
+  float ty = fmaxf(fmaxf(gmin.y - c.y, c.y - gmax.y), 0.0f);
+  float tz = fmaxf(fmaxf(gmin.z - c.z, c.z - gmax.z), 0.0f);
+  float d2 = (tx * tx + ty * ty) + tz * tz;
+  return d2 == 0.0f || d2 * th2 < c.w * c.w;
+}
+
+// One wave walks group g.  MODE 0 counts, MODE 1 writes at the offsets.
+// Q is the frontier storage (LDS, or a volatile global queue in the fallback).
+template <int MODE, typename Q>
+__device__ void walk_group(const DevTree& T, const WalkBufs& B, int64_t g, float th2, Q q,
+                           uint32_t qmask, int fallback) {
+  const int lane = threadIdx.x;
+  const float4* gbox = reinterpret_cast<const float4*>(T.gbox);
+  const int4* topo = reinterpret_cast<const int4*>(T.topo);
+  const float4* geo = reinterpret_cast<const float4*>(T.geo);
+  const float4 gmin = gbox[2 * g], gmax = gbox[2 * g + 1];
+  int nC = 0, nL = 0, nsrc = 0, ovf = 0;
+  int64_t cb = 0, lb = 0;
+  if (MODE == 1) {
+    cb = B.c_off[g];
+    lb = B.l_off[g];
+    if (B.c_off[g + 1] > B.cap_c || B.l_off[g + 1] > B.cap_l) {
+      if (lane == 0) atomicOr(reinterpret_cast<unsigned long long*>(&B.tot[4]), 1ull);
+      return;
+    }
+  }
+  const int4 root = topo[0];
+  if (root.y == 0) {  // the root is a leaf: every group sees all particles directly
+    nL = 1;
+    nsrc = root.w;
+    if (MODE == 1 && lane == 0) B.l_ids[lb] = 0;
+  } else {
+    uint32_t head = 0, tail = (uint32_t)root.y;
+    if (lane < root.y) q[lane] = root.x + lane;
+    if (fallback) __threadfence_block();
+    __syncthreads();
+    while (head < tail) {
+      const uint32_t navail = min(64u, tail - head);
+      const bool valid = (uint32_t)lane < navail;
+      const int c = valid ? (int)q[(head + lane) & qmask] : 0;
+      const float4 ge = geo[c];
+      const int4 tp = topo[c];
+      const bool op = open_cell(gmin, gmax, ge, th2);
+      const bool toC = valid && !op;
+      const bool toL = valid && op && tp.y == 0;
+      const bool push = valid && op && tp.y != 0;
+      const uint64_t mC = __ballot(toC), mL = __ballot(toL);
+      if (MODE == 1) {
+        if (toC) B.c_ids[cb + nC + rank_below(mC)] = c;
+        if (toL) B.l_ids[lb + nL + rank_below(mL)] = c;
+      } else {
+        nsrc += wave_sum(toL ? tp.w : 0);
+      }
+      nC += __popcll(mC);
+      nL += __popcll(mL);
+      // Exclusive prefix of the children counts (each <= 8) over the lanes,
+      // from one ballot per bit.
+      const int nch = push ? tp.y : 0;
+      int pre = 0, tot = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const uint64_t m = __ballot((nch >> b) & 1);
+        pre += rank_below(m) << b;
+        tot += __popcll(m) << b;
+      }
+      head += navail;
+      if (tail + (uint32_t)tot - head > qmask + 1) {
+        ovf = 1;
+        break;
+      }
+      __syncthreads();
+      for (int j = 0; j < nch; ++j) q[(tail + pre + j) & qmask] = tp.x + j;
+      tail += (uint32_t)tot;
+      if (fallback) __threadfence_block();
+      __syncthreads();
+    }
+  }
+  if (MODE == 0 && lane == 0) {
+    int4 r;
+    r.x = nC;
+    r.y = nL;
+    r.z = nsrc;
+    r.w = (ovf || fallback) ? 1 : 0;
+    reinterpret_cast<int4*>(B.cnt)[g] = r;
+    if (ovf && !fallback) B.ovf_list[atomicAdd(B.ovf_count, 1)] = (int32_t)g;
+  }
+  if (ovf && fallback && lane == 0)
+    atomicOr(reinterpret_cast<unsigned long long*>(&B.tot[5]), 1ull);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(64) void walk_kernel(DevTree T, WalkBufs B, float th2) {
+  __shared__ int q[kQueueLds];
+  const int64_t g = xcd_slab(blockIdx.x, gridDim.x, T.ng);
+  if (g < 0) return;
+  if (MODE == 1 && B.cnt[4 * g + 3]) return;  // walked by the fallback
+  walk_group<MODE>(T, B, g, th2, q, (uint32_t)min(B.lds_qcap, kQueueLds) - 1, 0);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(64) void walk_fallback_kernel(DevTree T, WalkBufs B, float th2) {
+  const int n = *B.ovf_count;
+  volatile int32_t* q = B.gq + (int64_t)blockIdx.x * B.gq_cap;
+  for (int i = blockIdx.x; i < n; i += gridDim.x)
+    walk_group<MODE>(T, B, B.ovf_list[i], th2, q, (uint32_t)(B.gq_cap - 1), 1);
+}
+
+__global__ void walk_init_kernel(WalkBufs B) {
+  if (threadIdx.x < 8) B.tot[threadIdx.x] = 0;
+  if (threadIdx.x == 0) *B.ovf_count = 0;
+}
+
+// ----------------------------------------------------------------- offsets
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+// Exclusive scan of one int64 per thread over a 256-thread block.
+__device__ int64_t block_excl_scan(int64_t v, int64_t* sh, int64_t* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    int64_t a = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  int64_t incl = sh[t];
+  *total = sh[kScanThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(DevTree T, WalkBufs B) {
+  __shared__ int64_t sh[4 * kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  int64_t sc = 0, sl = 0, npc = 0, npp = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t g = base + threadIdx.x + k * kScanThreads;
+    if (g < T.ng) {
+      const int4 c = reinterpret_cast<const int4*>(B.cnt)[g];
+      const int64_t sz = T.ginfo[4 * g + 1];
+      sc += c.x;
+      sl += c.y;
+      npc += sz * c.x;
+      npp += sz * c.z;
+    }
+  }
+  int64_t* s = sh + threadIdx.x;
+  s[0] = sc;
+  s[kScanThreads] = sl;
+  s[2 * kScanThreads] = npc;
+  s[3 * kScanThreads] = npp;
+  __syncthreads();
+  for (int o = kScanThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int k = 0; k < 4; ++k) s[k * kScanThreads] += s[k * kScanThreads + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    B.blk[2 * blockIdx.x] = sh[0];
+    B.blk[2 * blockIdx.x + 1] = sh[kScanThreads];
+    atomicAdd(reinterpret_cast<unsigned long long*>(&B.tot[2]), (unsigned long long)sh[2 * kScanThreads]);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&B.tot[3]), (unsigned long long)sh[3 * kScanThreads]);
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(DevTree T, WalkBufs B) {
+  __shared__ int64_t sh[kScanThreads];
+  // Offset of this block: the sum of all earlier blocks' totals.
+  int64_t pc = 0, pl = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanThreads) {
+    pc += B.blk[2 * b];
+    pl += B.blk[2 * b + 1];
+  }
+  int64_t tc, tl;
+  block_excl_scan(pc, sh, &tc);
+  block_excl_scan(pl, sh, &tl);
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+  int64_t vc[kScanItems], vl[kScanItems], sc = 0, sl = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t g = base + k;
+    int4 c = g < T.ng ? reinterpret_cast<const int4*>(B.cnt)[g] : make_int4(0, 0, 0, 0);
+    vc[k] = c.x;
+    vl[k] = c.y;
+    sc += c.x;
+    sl += c.y;
+  }
+  int64_t bc, bl;
+  int64_t xc = block_excl_scan(sc, sh, &bc) + tc;
+  int64_t xl = block_excl_scan(sl, sh, &bl) + tl;
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t g = base + k;
+    if (g < T.ng) {
+      B.c_off[g] = xc;
+      B.l_off[g] = xl;
+    }
+    xc += vc[k];
+    xl += vl[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
+    B.c_off[T.ng] = tc + bc;
+    B.l_off[T.ng] = tl + bl;
+    B.tot[0] = tc + bc;
+    B.tot[1] = tl + bl;
+  }
+}
+
+}  // namespace
+
+int64_t scan_scratch_entries(int64_t ng) { return 2 * ((ng + kScanBlock - 1) / kScanBlock + 1); }
+
+int launch_walk(const DevTree& T, const WalkBufs& B, float theta, int mode, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const float th2 = theta * theta;
+  const int64_t grid = ((T.ng + 7) / 8) * 8;
+  if (mode == 0) {
+    walk_init_kernel<<<1, 64, 0, s>>>(B);
+    walk_kernel<0><<<grid, 64, 0, s>>>(T, B, th2);
+    walk_fallback_kernel<0><<<B.gq_waves, 64, 0, s>>>(T, B, th2);
+  } else {
+    walk_kernel<1><<<grid, 64, 0, s>>>(T, B, th2);
+    walk_fallback_kernel<1><<<B.gq_waves, 64, 0, s>>>(T, B, th2);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_scan(const DevTree& T, const WalkBufs& B, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = (int)((T.ng + kScanBlock - 1) / kScanBlock);
+  scan_reduce_kernel<<<nb, kScanThreads, 0, s>>>(T, B);
+  scan_apply_kernel<<<nb, kScanThreads, 0, s>>>(T, B);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int fallback_waves() { return kFallbackWaves; }
+
+}  // namespace octgrav

@@ -1,0 +1,184 @@
+"""Thin Python binding of the C ABI in include/octgrav.h (ctypes).
+
+Argument marshalling only: every step of the force computation runs in the
+HIP library.  PyTorch provides device memory and the stream.  Loading fails
+loudly when the built library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libocgrav.so")
+
+OK, EINVAL, ENOMEM, EHIP, ECAPACITY = 0, -1, -2, -3, -4
+BUILD_HOST_ONLY = 1
+PLAIN_SUM = 1
+TIMED = 2
+
+_lib = None
+
+
+class OctgravError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"octgrav error {code}: {msg}")
+        self.code = code
+
+
+class Stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("n", "n_cells", "n_leaves", "n_groups", "max_depth",
+                                         "max_level_cells", "n_work", "n_leaf", "n_group")]
+
+
+class TreeView(C.Structure):
+    _fields_ = [("perm", C.c_void_p), ("topo", C.c_void_p), ("geo", C.c_void_p),
+                ("mp", C.c_void_p), ("mp64", C.c_void_p), ("box", C.c_void_p),
+                ("depth", C.c_void_p), ("groups", C.c_void_p), ("cube", C.c_void_p)]
+
+
+EXPORTED = ["octgrav_build_tree", "octgrav_build_tree_ex", "octgrav_forces", "octgrav_forces_ex",
+            "octgrav_free", "octgrav_last_error", "octgrav_set_stream", "octgrav_tree_stats",
+            "octgrav_export_tree", "octgrav_lists", "octgrav_diagnostics", "octgrav_last_counts",
+            "octgrav_last_timings"]
+
+
+def lib():
+    """The loaded libocgrav.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes this library bind to that one runtime, so torch's
+        # streams and allocations are valid handles here.
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, f32 = C.c_void_p, C.c_int64, C.c_int32, C.c_float
+        L.octgrav_build_tree.restype = vp
+        L.octgrav_build_tree.argtypes = [vp, vp, i64, i32]
+        L.octgrav_build_tree_ex.restype = vp
+        L.octgrav_build_tree_ex.argtypes = [vp, vp, i64, i32, i32, C.c_uint32]
+        L.octgrav_forces.argtypes = [vp, f32, f32, vp, vp]
+        L.octgrav_forces_ex.argtypes = [vp, f32, f32, vp, vp, C.c_uint32]
+        L.octgrav_free.argtypes = [vp]
+        L.octgrav_free.restype = None
+        L.octgrav_last_error.restype = C.c_char_p
+        L.octgrav_set_stream.argtypes = [vp, vp]
+        L.octgrav_tree_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.octgrav_export_tree.argtypes = [vp, C.POINTER(TreeView)]
+        L.octgrav_lists.argtypes = [vp, f32, vp, vp, vp, vp, C.POINTER(i64), C.POINTER(i64)]
+        L.octgrav_diagnostics.argtypes = [vp, vp, vp]
+        L.octgrav_last_counts.argtypes = [vp, vp]
+        L.octgrav_last_timings.argtypes = [vp, vp]
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().octgrav_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise OctgravError(rc, last_error())
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+class Tree:
+    """A built tree (host FP64 build + device upload) and its force calls."""
+
+    def __init__(self, pos, mass, n_leaf=16, n_group=64, host_only=False):
+        pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+        mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
+        self.n = pos.shape[0]
+        if mass.shape[0] != self.n:
+            raise ValueError("pos and mass disagree on n")
+        h = lib().octgrav_build_tree_ex(_ptr(pos), _ptr(mass), self.n, int(n_leaf), int(n_group),
+                                        BUILD_HOST_ONLY if host_only else 0)
+        if not h:
+            raise OctgravError(EINVAL, last_error())
+        self._h = C.c_void_p(h)
+        s = Stats()
+        _check(lib().octgrav_tree_stats(self._h, C.byref(s)))
+        self.stats = {k: int(getattr(s, k)) for k, _ in Stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.octgrav_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _bind_stream(self):
+        import torch
+        _check(lib().octgrav_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def forces(self, theta, eps, acc=None, pot=None, plain=False, timed=False, with_pot=True):
+        """(acc [n,3], pot [n]) as float32 torch tensors on the current device."""
+        import torch
+        if acc is None:
+            acc = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
+        if pot is None and with_pot:
+            pot = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        for t in (acc, pot):
+            if t is not None and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("acc/pot must be contiguous float32 CUDA tensors")
+        if acc.numel() != 3 * self.n or (pot is not None and pot.numel() != self.n):
+            raise ValueError("acc must hold n*3 and pot n elements")
+        self._bind_stream()
+        flags = (PLAIN_SUM if plain else 0) | (TIMED if timed else 0)
+        _check(lib().octgrav_forces_ex(self._h, float(theta), float(eps), C.c_void_p(acc.data_ptr()),
+                                       None if pot is None else C.c_void_p(pot.data_ptr()), flags))
+        return acc, pot
+
+    def lists(self, theta):
+        """(c_off, c_ids, l_off, l_ids) numpy CSR lists built by the GPU walk."""
+        self._bind_stream()
+        nc, nl = C.c_int64(), C.c_int64()
+        _check(lib().octgrav_lists(self._h, float(theta), None, None, None, None,
+                                   C.byref(nc), C.byref(nl)))
+        ng = self.stats["n_groups"]
+        c_off = np.zeros(ng + 1, np.int64)
+        l_off = np.zeros(ng + 1, np.int64)
+        c_ids = np.zeros(max(1, nc.value), np.int32)
+        l_ids = np.zeros(max(1, nl.value), np.int32)
+        _check(lib().octgrav_lists(self._h, float(theta), _ptr(c_off), _ptr(c_ids), _ptr(l_off),
+                                   _ptr(l_ids), C.byref(nc), C.byref(nl)))
+        return c_off, c_ids[:nc.value], l_off, l_ids[:nl.value]
+
+    def export(self):
+        s = self.stats
+        n, nc, ng = s["n"], s["n_cells"], s["n_groups"]
+        out = dict(perm=np.zeros(n, np.int32), topo=np.zeros((nc, 4), np.int32),
+                   geo=np.zeros((nc, 4), np.float32), mp=np.zeros((nc, 12), np.float32),
+                   mp64=np.zeros((nc, 10)), box=np.zeros((nc, 6)), depth=np.zeros(nc, np.int32),
+                   groups=np.zeros(ng, np.int32), cube=np.zeros(4))
+        v = TreeView(*(_ptr(out[k]) for k, _ in TreeView._fields_))
+        _check(lib().octgrav_export_tree(self._h, C.byref(v)))
+        return out
+
+    def diagnostics(self):
+        """(momentum sum m a [3], W = 1/2 sum m phi) in FP64 from the last forces call."""
+        mom = np.zeros(3)
+        w = np.zeros(1)
+        _check(lib().octgrav_diagnostics(self._h, _ptr(mom), _ptr(w)))
+        return mom, float(w[0])
+
+    def last_counts(self):
+        out = np.zeros(4, np.int64)
+        _check(lib().octgrav_last_counts(self._h, _ptr(out)))
+        return dict(n_c=int(out[0]), n_l=int(out[1]), n_pc=int(out[2]), n_pp=int(out[3]))
+
+    def last_timings(self):
+        out = np.zeros(6)
+        _check(lib().octgrav_last_timings(self._h, _ptr(out)))
+        return dict(zip(("walk_count", "offsets", "walk_write", "eval", "diag", "total"),
+                        out.tolist()))

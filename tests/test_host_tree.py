@@ -1,0 +1,161 @@
+"""CPU tests of the library's host side: its tree against the oracle's
+independently built tree, the C ABI's argument checks and error paths, and
+the exported symbols.  No GPU call is made (host-only builds)."""
+import ctypes as C
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1005_5384_amd import octgrav as og
+from paper_1005_5384_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _same_tree(pos, m, n_leaf, n_group):
+    T = og.Tree(pos, m, n_leaf, n_group, host_only=True)
+    O = oracle.Tree(pos, m, n_leaf, n_group)
+    e, o = T.export(), O.export()
+    assert T.stats["n_cells"] == O.n_cells and T.stats["n_groups"] == O.n_groups
+    assert T.stats["max_depth"] == O.max_depth
+    assert np.array_equal(e["perm"], o["order"])
+    for k in ("topo", "geo", "depth", "groups", "box", "cube"):
+        assert np.array_equal(e[k], o[k]), k
+    # FP64 moments agree to rounding; their FP32 images to 1 ulp at most.
+    scale = o["mp"][:, :1] * np.maximum(e["geo"][:, 3:4].astype(np.float64), 1e-30) ** 2
+    assert np.all(np.abs(e["mp64"][:, 0] - o["mp"][:, 0]) <= 1e-13 * o["mp"][:, 0])
+    assert np.all(np.abs(e["mp64"][:, 1:4] - o["mp"][:, 1:4]) <= 1e-12 * (1 + np.abs(o["mp"][:, 1:4])))
+    assert np.all(np.abs(e["mp64"][:, 4:] - o["mp"][:, 4:]) <= 1e-12 * scale + 1e-300)
+    ref32 = np.concatenate([o["mp"][:, 1:4], o["mp"][:, :1], o["mp"][:, 4:]], 1).astype(np.float32)
+    ulp = np.abs(e["mp"][:, :10].view(np.int32).astype(np.int64) - ref32.view(np.int32).astype(np.int64))
+    small = np.abs(ref32) < 1e-30  # sign flips of values that round to ~0
+    assert np.all((ulp <= 1) | small)
+    return T, O
+
+
+@pytest.mark.parametrize("n,n_leaf,n_group,seed", [
+    (1, 16, 64, 1), (2, 1, 1, 2), (7, 16, 64, 3), (16384, 16, 64, 101), (3000, 1, 1, 5),
+    (2500, 8, 32, 7), (5000, 64, 64, 8), (20000, 32, 64, 9)])
+def test_tree_matches_oracle_plummer(n, n_leaf, n_group, seed):
+    pos, m = W.plummer(n, seed)
+    _same_tree(pos, m, n_leaf, n_group)
+
+
+def test_tree_matches_oracle_clumps_and_galaxy():
+    pos, m = W.plummer_clumps(30000, 103)
+    _same_tree(pos, m, 32, 64)
+    pos, m = W.galaxy_mix(30000, 108, n_clumps=16)
+    _same_tree(pos, m, 32, 64)
+
+
+def test_tree_matches_oracle_unequal_masses_and_offsets():
+    rng = np.random.default_rng(3)
+    pos = (rng.normal(size=(4000, 3)) * [1e3, 1e-2, 5.0] + [1e5, -3.0, 7e-3]).astype(np.float32)
+    m = rng.lognormal(0, 2, 4000).astype(np.float32)
+    _same_tree(pos, m, 16, 64)
+
+
+def test_tree_matches_oracle_degenerate():
+    # coincident stacks (depth-21 leaves, groups larger than 64), a flat
+    # sheet, exact plane ties on a lattice
+    pos = np.zeros((300, 3), np.float32)
+    pos[100:] = [1, 1, 1]
+    pos[250:] = [1, 1, 1.5]
+    m = np.full(300, 1 / 300, np.float32)
+    T, _ = _same_tree(pos, m, 8, 64)
+    assert T.stats["max_depth"] == 21 and T.stats["n_work"] > T.stats["n_groups"]
+    g = np.mgrid[0:8, 0:8, 0:1].reshape(3, -1).T.astype(np.float32)
+    _same_tree(g, np.ones(64, np.float32), 2, 4)
+    lat = np.mgrid[0:6, 0:6, 0:6].reshape(3, -1).T.astype(np.float32) * 0.25
+    _same_tree(lat, np.ones(216, np.float32), 3, 9)
+
+
+def test_work_items_split_large_groups():
+    pos = np.zeros((150, 3), np.float32)
+    T = og.Tree(pos, np.ones(150, np.float32), 16, 64, host_only=True)
+    assert T.stats["n_groups"] == 1 and T.stats["n_work"] == 3
+
+
+# ---------------------------------------------------------------- C ABI
+def test_exported_symbols_match_header():
+    hdr = open(os.path.join(ROOT, "include", "octgrav.h")).read()
+    declared = set(re.findall(r"\b(octgrav_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == set(og.EXPORTED)
+    L = og.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", og.LIB_PATH], capture_output=True, text=True)
+    syms = {ln.split()[-1] for ln in out.stdout.splitlines() if " T " in ln}
+    assert declared <= syms
+
+
+def test_build_rejects_bad_input():
+    pos, m = W.plummer(100, 1)
+    bad = [
+        (pos, m, 0, 64), (pos, m, 65, 64), (pos, m, 16, 0), (pos, m, 16, 2000),
+    ]
+    for p, mm, nl, ng in bad:
+        with pytest.raises(og.OctgravError):
+            og.Tree(p, mm, nl, ng, host_only=True)
+    p2 = pos.copy()
+    p2[5, 1] = np.nan
+    with pytest.raises(og.OctgravError, match="finite"):
+        og.Tree(p2, m, host_only=True)
+    p2 = pos.copy()
+    p2[5, 1] = 2.0 ** 61
+    with pytest.raises(og.OctgravError, match="2\\^60"):
+        og.Tree(p2, m, host_only=True)
+    m2 = m.copy()
+    m2[3] = 0.0
+    with pytest.raises(og.OctgravError, match="mass"):
+        og.Tree(pos, m2, host_only=True)
+    L = og.lib()
+    assert not L.octgrav_build_tree(None, None, 10, 16)
+    assert "NULL" in og.last_error()
+    assert not L.octgrav_build_tree(pos.ctypes.data, m.ctypes.data, 0, 16)
+
+
+def test_host_only_handle_rejects_device_calls():
+    pos, m = W.plummer(100, 1)
+    T = og.Tree(pos, m, host_only=True)
+    L = og.lib()
+    rc = L.octgrav_forces(T._h, 0.5, 0.01, C.c_void_p(16), None)
+    assert rc == og.EINVAL and "host-only" in og.last_error()
+    nc, nl = C.c_int64(), C.c_int64()
+    assert L.octgrav_lists(T._h, 0.5, None, None, None, None, C.byref(nc), C.byref(nl)) == og.EINVAL
+    mom = np.zeros(3)
+    w = np.zeros(1)
+    assert L.octgrav_diagnostics(T._h, mom.ctypes.data, w.ctypes.data) == og.EINVAL
+    out = np.zeros(4, np.int64)
+    assert L.octgrav_last_counts(T._h, out.ctypes.data) == og.EINVAL
+
+
+def test_null_handles_are_rejected():
+    L = og.lib()
+    L.octgrav_free(None)  # no-op
+    assert L.octgrav_forces(None, 0.5, 0.01, None, None) == og.EINVAL
+    assert L.octgrav_set_stream(None, None) == og.EINVAL
+    s = og.Stats()
+    assert L.octgrav_tree_stats(None, C.byref(s)) == og.EINVAL
+    assert L.octgrav_export_tree(None, None) == og.EINVAL
+
+
+def test_allocation_failure_is_reported():
+    # Injected device-allocation failure: the build must fail cleanly with
+    # ENOMEM before touching the GPU.
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import numpy as np\n"
+            "from paper_1005_5384_amd import octgrav as og, workloads as W\n"
+            "pos, m = W.plummer(64, 1)\n"
+            "h = og.lib().octgrav_build_tree(pos.ctypes.data, m.ctypes.data, 64, 16)\n"
+            "print('NULL' if not h else 'HANDLE', og.last_error())\n") % ROOT
+    env = dict(os.environ, OCTGRAV_FAIL_ALLOC="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.startswith("NULL") and "injected" in r.stdout
