@@ -47,6 +47,8 @@ extern "C" {
 /* octgrav_forces_ex flags */
 #define OCTGRAV_PLAIN_SUM 1u /* plain FP32 accumulation instead of compensated */
 #define OCTGRAV_TIMED 2u     /* record HIP events around each kernel phase */
+#define OCTGRAV_TWO_PASS 4u  /* separate count walk, offsets, write walk and evaluation kernels
+                                (the paper's structure) instead of the fused walk+evaluation */
 
 typedef struct octgrav_tree octgrav_tree;
 
@@ -57,7 +59,7 @@ typedef struct {
   int64_t n_groups;        /* particle groups (walk units) */
   int64_t max_depth;       /* deepest cell level (root = 0, at most 21) */
   int64_t max_level_cells; /* most cells on one level */
-  int64_t n_work;          /* evaluation work items (groups split in chunks of 64) */
+  int64_t n_work;          /* evaluation work items (groups split in chunks of 32 targets) */
   int64_t n_leaf, n_group; /* build parameters */
 } octgrav_stats;
 
@@ -131,14 +133,21 @@ int octgrav_export_tree(const octgrav_tree* t, const octgrav_tree_view* v);
 
 /*
  * Interaction lists of every group at opening angle theta, built by the GPU
- * walk (Sec. 2.2: a count walk, offsets, a write walk) and copied to the host
- * in CSR form over groups; ids are cell ids in ascending order.  Two-call
- * pattern: with c_off/c_ids/l_off/l_ids NULL only *n_c and *n_l (total
- * entries) are set; otherwise c_off and l_off hold n_groups+1 int64 each and
- * c_ids/l_ids at least *n_c / *n_l int32 entries.
+ * walk (Sec. 2.2) and copied to the host in CSR form over groups; ids are
+ * cell ids in ascending order.  Sizes and offsets come from the count walk
+ * and the device prefix sum; the entries are written by the same walk the
+ * default force path runs (the fused walk+evaluation, with evaluation
+ * skipped).  Two-call pattern: with c_off/c_ids/l_off/l_ids NULL only *n_c
+ * and *n_l (total entries) are set; otherwise c_off and l_off hold
+ * n_groups+1 int64 each and c_ids/l_ids at least *n_c / *n_l int32 entries.
  */
 int octgrav_lists(octgrav_tree* t, float theta, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
                   int32_t* l_ids, int64_t* n_c, int64_t* n_l);
+
+/* As octgrav_lists; flags OCTGRAV_TWO_PASS takes the entries from the
+ * separate write walk instead. */
+int octgrav_lists_ex(octgrav_tree* t, float theta, uint32_t flags, int64_t* c_off, int32_t* c_ids,
+                     int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l);
 
 /* FP64 diagnostics of the last octgrav_forces call, reduced on the GPU:
  * mom = sum_i m_i a_i and *w = 1/2 sum_i m_i phi_i (0 if pot was NULL). */
@@ -152,7 +161,9 @@ int octgrav_last_counts(octgrav_tree* t, int64_t out[4]);
 
 /* Kernel-phase times in ms of the last OCTGRAV_TIMED forces call, measured
  * with HIP events on the handle's stream: out[0] count walk, out[1] offsets,
- * out[2] write walk, out[3] evaluation, out[4] diagnostics, out[5] total. */
+ * out[2] write walk, out[3] evaluation (in the default fused path: walk and
+ * evaluation together; out[0..2] are then 0), out[4] diagnostics,
+ * out[5] total. */
 int octgrav_last_timings(octgrav_tree* t, double out[6]);
 
 #ifdef __cplusplus

@@ -36,12 +36,13 @@ bool alloc_fault() {
   return v && v[0] == '1';
 }
 
-// Set by OCTGRAV_LDS_QUEUE=<power of two> (test-only): shrinks the walk's
-// LDS frontier so that groups overflow into the global-memory fallback walk.
+// Set by OCTGRAV_LDS_QUEUE=<power of two> (test-only): caps the walks' LDS
+// frontier queues so that groups overflow into the global-memory fallback
+// walks.  Unset, the kernels use their full queues.
 int lds_queue_entries() {
   const char* v = std::getenv("OCTGRAV_LDS_QUEUE");
-  int q = v ? std::atoi(v) : 2048;
-  if (q < 64 || q > 2048 || (q & (q - 1))) q = 2048;
+  int q = v ? std::atoi(v) : (1 << 20);
+  if (q < 64 || (q & (q - 1))) q = 1 << 20;
   return q;
 }
 
@@ -102,8 +103,21 @@ struct octgrav_tree {
     dt.ng = ng;
     dt.nw = nw;
     int rc;
+    // Device boundary sides carry the leaf flag in their sign bit (the
+    // opening test squares the side, so its decisions are unchanged).
+    std::vector<float> geo_dev(h.geo);
+    for (int64_t c = 0; c < nc; ++c)
+      if (h.topo[4 * c + 1] == 0) geo_dev[4 * c + 3] = -geo_dev[4 * c + 3];
+    // Walk record: the boundary and the topology of a cell in one 32-byte
+    // line, so one gather serves a candidate's test and its expansion.
+    std::vector<float> wrec((size_t)nc * 8);
+    for (int64_t c = 0; c < nc; ++c) {
+      std::memcpy(&wrec[8 * c], &geo_dev[4 * c], 16);
+      std::memcpy(&wrec[8 * c + 4], &h.topo[4 * c], 16);
+    }
     if ((rc = upload(h.part, &dt.part)) || (rc = upload(h.perm, &dt.perm)) ||
-        (rc = upload(h.topo, &dt.topo)) || (rc = upload(h.geo, &dt.geo)) ||
+        (rc = upload(h.topo, &dt.topo)) || (rc = upload(geo_dev, &dt.geo)) ||
+        (rc = upload(wrec, &dt.wrec)) ||
         (rc = upload(h.mp, &dt.mp)) || (rc = upload(h.ginfo, &dt.ginfo)) ||
         (rc = upload(h.gbox, &dt.gbox)) || (rc = upload(h.work, &dt.work)))
       return rc;
@@ -118,7 +132,7 @@ struct octgrav_tree {
     wb.tot = (int64_t*)p;
     if ((rc = dalloc(&p, (size_t)scan_scratch_entries(ng) * 8))) return rc;
     wb.blk = (int64_t*)p;
-    if ((rc = dalloc(&p, (size_t)ng * 4))) return rc;
+    if ((rc = dalloc(&p, (size_t)std::max(ng, nw) * 4))) return rc;
     wb.ovf_list = (int32_t*)p;
     if ((rc = dalloc(&p, 4))) return rc;
     wb.ovf_count = (int32_t*)p;
@@ -132,6 +146,7 @@ struct octgrav_tree {
     if ((rc = dalloc(&p, (size_t)wb.gq_waves * cap * 4))) return rc;
     wb.gq = (int32_t*)p;
     wb.lds_qcap = lds_queue_entries();
+    wb.export_lists = 0;
     wb.cap_c = wb.cap_l = 0;
     wb.c_ids = wb.l_ids = nullptr;
     if ((rc = dalloc(&p, (size_t)diag_scratch_entries(n) * 8))) return rc;
@@ -295,39 +310,50 @@ int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float
     const bool timed = flags & OCTGRAV_TIMED, plain = flags & OCTGRAV_PLAIN_SUM;
     t->counts_valid = false;
     t->have_diag = false;
-    if (int rc = t->lists_on_device(theta, timed)) return rc;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-      if (launch_eval(t->dt, t->wb, eps, plain, acc, pot, t->stream))
-        return fail(OCTGRAV_EHIP, "evaluation launch failed");
-      if (timed) hipEventRecord(t->ev[4], t->stream);
-      if (launch_diag(t->dt, acc, pot, t->d_diag_part, t->d_diag, t->stream))
-        return fail(OCTGRAV_EHIP, "diagnostics launch failed");
-      if (timed) hipEventRecord(t->ev[5], t->stream);
-      int64_t tot[8];
-      if (int rc = t->read_tot(tot)) return rc;
-      if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
-      if (tot[0] <= t->wb.cap_c && tot[1] <= t->wb.cap_l) {
-        t->counts_valid = true;
-        t->have_diag = true;
-        if (timed) {
-          float ms;
-          for (int k = 0; k < 5; ++k) {
-            hipEventElapsedTime(&ms, t->ev[k], t->ev[k + 1]);
-            t->timings[k] = ms;
-          }
-          hipEventElapsedTime(&ms, t->ev[0], t->ev[5]);
-          t->timings[5] = ms;
-        }
-        return OCTGRAV_OK;
+    int64_t tot[8];
+    if (!(flags & OCTGRAV_TWO_PASS)) {
+      // Fused walk + evaluation: no lists in memory, no host round trip.
+      t->wb.export_lists = 0;
+      if (timed) {
+        for (int k = 0; k < 4; ++k) hipEventRecord(t->ev[k], t->stream);
       }
-      // Lists outgrew the buffers of an earlier call: grow and rewrite.
-      if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
-      if (timed) hipEventRecord(t->ev[2], t->stream);
-      if (launch_walk(t->dt, t->wb, theta, 1, t->stream))
-        return fail(OCTGRAV_EHIP, "write walk launch failed");
-      if (timed) hipEventRecord(t->ev[3], t->stream);
+      if (launch_walk_eval(t->dt, t->wb, theta, eps, plain, true, acc, pot, t->stream))
+        return fail(OCTGRAV_EHIP, "walk+evaluation launch failed");
+      if (timed) hipEventRecord(t->ev[4], t->stream);
+    } else {
+      if (int rc = t->lists_on_device(theta, timed)) return rc;
+      for (int attempt = 0;; ++attempt) {
+        if (launch_eval(t->dt, t->wb, eps, plain, acc, pot, t->stream))
+          return fail(OCTGRAV_EHIP, "evaluation launch failed");
+        if (timed) hipEventRecord(t->ev[4], t->stream);
+        if (int rc = t->read_tot(tot)) return rc;
+        if (tot[0] <= t->wb.cap_c && tot[1] <= t->wb.cap_l) break;
+        if (attempt == 1) return fail(OCTGRAV_ECAPACITY, "list capacity still exceeded after retry");
+        // Lists outgrew the buffers of an earlier call: grow and rewrite.
+        if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
+        if (timed) hipEventRecord(t->ev[2], t->stream);
+        if (launch_walk(t->dt, t->wb, theta, 1, t->stream))
+          return fail(OCTGRAV_EHIP, "write walk launch failed");
+        if (timed) hipEventRecord(t->ev[3], t->stream);
+      }
     }
-    return fail(OCTGRAV_ECAPACITY, "list capacity still exceeded after retry");
+    if (launch_diag(t->dt, acc, pot, t->d_diag_part, t->d_diag, t->stream))
+      return fail(OCTGRAV_EHIP, "diagnostics launch failed");
+    if (timed) hipEventRecord(t->ev[5], t->stream);
+    if (int rc = t->read_tot(tot)) return rc;
+    if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+    t->counts_valid = true;
+    t->have_diag = true;
+    if (timed) {
+      float ms;
+      for (int k = 0; k < 5; ++k) {
+        hipEventElapsedTime(&ms, t->ev[k], t->ev[k + 1]);
+        t->timings[k] = ms;
+      }
+      hipEventElapsedTime(&ms, t->ev[0], t->ev[5]);
+      t->timings[5] = ms;
+    }
+    return OCTGRAV_OK;
   } catch (const std::exception& e) {
     return fail(OCTGRAV_EHIP, e.what());
   }
@@ -337,8 +363,8 @@ int octgrav_forces(octgrav_tree* t, float theta, float eps, float* acc, float* p
   return octgrav_forces_ex(t, theta, eps, acc, pot, 0);
 }
 
-int octgrav_lists(octgrav_tree* t, float theta, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
-                  int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
+int octgrav_lists_ex(octgrav_tree* t, float theta, uint32_t flags, int64_t* c_off, int32_t* c_ids,
+                     int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
   g_err.clear();
   if (int rc = check_theta(t, theta)) return rc;
   if (!n_c || !n_l) return fail(OCTGRAV_EINVAL, "n_c and n_l must be non-NULL");
@@ -348,17 +374,28 @@ int octgrav_lists(octgrav_tree* t, float theta, int64_t* c_off, int32_t* c_ids, 
   try {
     t->counts_valid = false;
     int64_t tot[8];
-    for (int attempt = 0; attempt < 2; ++attempt) {
-      if (int rc = t->lists_on_device(theta, false)) return rc;
-      if (int rc = t->read_tot(tot)) return rc;
-      if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
-      if (tot[0] <= t->wb.cap_c && tot[1] <= t->wb.cap_l) break;
-      if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
-      if (attempt == 1) return fail(OCTGRAV_ECAPACITY, "list capacity exceeded");
-    }
-    t->counts_valid = true;
+    // Count walk and offsets give the sizes; the buffers are made to fit.
+    if (launch_walk(t->dt, t->wb, theta, 0, t->stream)) return fail(OCTGRAV_EHIP, "count walk launch failed");
+    if (launch_scan(t->dt, t->wb, t->stream)) return fail(OCTGRAV_EHIP, "offsets launch failed");
+    if (int rc = t->read_tot(tot)) return rc;
+    if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+    if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
     *n_c = tot[0];
     *n_l = tot[1];
+    if (flags & OCTGRAV_TWO_PASS) {
+      if (launch_walk(t->dt, t->wb, theta, 1, t->stream)) return fail(OCTGRAV_EHIP, "write walk launch failed");
+    } else {
+      t->wb.export_lists = 1;
+      int rc = launch_walk_eval(t->dt, t->wb, theta, 1.0f, false, false, nullptr, nullptr, t->stream);
+      t->wb.export_lists = 0;
+      if (rc) return fail(OCTGRAV_EHIP, "walk (export) launch failed");
+    }
+    int64_t tot2[8];
+    if (int rc = t->read_tot(tot2)) return rc;
+    if (tot2[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+    if (tot2[0] != tot[0] || tot2[1] != tot[1])
+      return fail(OCTGRAV_ECAPACITY, "walk list sizes disagree with the count walk");
+    t->counts_valid = true;
     if (want) {
       const int64_t ng = t->h.n_groups();
       if (hipMemcpy(c_off, t->wb.c_off, (ng + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -371,6 +408,11 @@ int octgrav_lists(octgrav_tree* t, float theta, int64_t* c_off, int32_t* c_ids, 
   } catch (const std::exception& e) {
     return fail(OCTGRAV_EHIP, e.what());
   }
+}
+
+int octgrav_lists(octgrav_tree* t, float theta, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
+                  int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
+  return octgrav_lists_ex(t, theta, 0, c_off, c_ids, l_off, l_ids, n_c, n_l);
 }
 
 int octgrav_diagnostics(octgrav_tree* t, double mom[3], double* w) {

@@ -1,0 +1,128 @@
+// Device helpers shared by the walk and evaluation kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace octgrav {
+namespace dev {
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ int rank_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous (Morton-ordered, hence spatially coherent) range of work so that
+// neighbouring groups share the XCD's L2.  nblocks is a multiple of 8.
+__device__ __forceinline__ int64_t xcd_slab(int64_t b, int64_t nblocks, int64_t n) {
+  int64_t per = nblocks >> 3;
+  int64_t i = (b & 7) * per + (b >> 3);
+  return i < n ? i : -1;
+}
+
+// Opening test (Sec. 2.2): open iff d2 == 0 or d2 * theta^2 < l^2, where d is
+// the distance from the cell's boundary centre to the group's tight box.
+// FP32, this exact operation order, no contraction: the decision is bit-exact
+// against any IEEE implementation of the same expression.
+__device__ __forceinline__ bool open_cell(float4 gmin, float4 gmax, float4 c, float th2) {
+#pragma clang fp contract(off)
+  float tx = fmaxf(fmaxf(gmin.x - c.x, c.x - gmax.x), 0.0f);
+  float ty = fmaxf(fmaxf(gmin.y - c.y, c.y - gmax.y), 0.0f);
+  float tz = fmaxf(fmaxf(gmin.z - c.z, c.z - gmax.z), 0.0f);
+  float d2 = (tx * tx + ty * ty) + tz * tz;
+  return d2 == 0.0f || d2 * th2 < c.w * c.w;
+}
+
+// Particle-particle (body-leaf) term: softened acceleration toward source j
+// and potential -m_j / r~, r~^2 = |x_j - x_i|^2 + eps^2.
+__device__ __forceinline__ void pp_term(const float4 xi, const float4 sj, float eps2, float& ax,
+                                        float& ay, float& az, float& ph) {
+  const float dx = sj.x - xi.x, dy = sj.y - xi.y, dz = sj.z - xi.z;
+  const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+  const float ri = __builtin_amdgcn_rsqf(r2);
+  const float mri = sj.w * ri;
+  const float mri3 = mri * (ri * ri);
+  ax = fmaf(mri3, dx, ax);
+  ay = fmaf(mri3, dy, ay);
+  az = fmaf(mri3, dz, az);
+  ph -= mri;
+}
+
+// Particle-cell (body-node) term: softened monopole + traceless quadrupole
+// about the cell's centre of mass, R = x_i - com, q = Q R, s = R.q:
+//   phi += -M/r~ - s/(2 r~^5),  a += -M R/r~^3 + q/r~^5 - 5 s R/(2 r~^7).
+// m0 = (com, M), m1 = (Qxx, Qyy, Qzz, Qxy), m2 = (Qxz, Qyz, -, -).
+__device__ __forceinline__ void pc_term(const float4 xi, const float4 m0, const float4 m1,
+                                        const float4 m2, float eps2, float& ax, float& ay,
+                                        float& az, float& ph) {
+  const float dx = xi.x - m0.x, dy = xi.y - m0.y, dz = xi.z - m0.z;
+  const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+  const float ri = __builtin_amdgcn_rsqf(r2);
+  const float ri2 = ri * ri;
+  const float qx = fmaf(m2.x, dz, fmaf(m1.w, dy, m1.x * dx));
+  const float qy = fmaf(m2.y, dz, fmaf(m1.y, dy, m1.w * dx));
+  const float qz = fmaf(m1.z, dz, fmaf(m2.y, dy, m2.x * dx));
+  const float s = fmaf(dz, qz, fmaf(dy, qy, dx * qx));
+  const float u = s * (ri2 * ri2);
+  ph = fmaf(-ri, fmaf(0.5f, u, m0.w), ph);
+  const float ri3 = ri * ri2;
+  const float c1 = -fmaf(2.5f, u, m0.w) * ri3;
+  const float c2 = ri3 * ri2;
+  ax = fmaf(c2, qx, fmaf(c1, dx, ax));
+  ay = fmaf(c2, qy, fmaf(c1, dy, ay));
+  az = fmaf(c2, qz, fmaf(c1, dz, az));
+}
+
+// Neumaier compensated addition of v into (s, c).
+__device__ __forceinline__ void neu_add(float& s, float& c, float v) {
+  const float t = s + v;
+  c += (fabsf(s) >= fabsf(v)) ? ((s - t) + v) : ((v - t) + s);
+  s = t;
+}
+
+// Per-lane accumulator: plain FP32 within a tile, folded per tile into a
+// compensated (sum, carry) pair unless PLAIN.
+struct Sum4 {
+  float s[4], c[4];
+  __device__ void zero() {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] = c[k] = 0.0f;
+  }
+  template <bool PLAIN>
+  __device__ void fold(float a0, float a1, float a2, float a3) {
+    if (PLAIN) {
+      s[0] += a0;
+      s[1] += a1;
+      s[2] += a2;
+      s[3] += a3;
+    } else {
+      neu_add(s[0], c[0], a0);
+      neu_add(s[1], c[1], a1);
+      neu_add(s[2], c[2], a2);
+      neu_add(s[3], c[3], a3);
+    }
+  }
+};
+
+// Every S-th entry of an LDS tile, starting at `first`, two at a time so the
+// compiler can overlap the LDS reads of one term with the arithmetic of the
+// other.
+template <typename F>
+__device__ __forceinline__ void strided2(int first, int cnt, int S, F&& f) {
+  int j = first;
+  for (; j + S < cnt; j += 2 * S) {
+    f(j);
+    f(j + S);
+  }
+  if (j < cnt) f(j);
+}
+
+}  // namespace dev
+}  // namespace octgrav

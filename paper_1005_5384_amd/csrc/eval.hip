@@ -14,88 +14,16 @@
 // in plain FP32 and folds it into a Neumaier-compensated (sum, carry) pair.
 #include <hip/hip_runtime.h>
 
+#include "device_common.h"
 #include "octgrav_internal.h"
 
 namespace octgrav {
 namespace {
 
+using namespace dev;
+
 constexpr int kThreads = 256;
 constexpr int kTile = 256;
-
-__device__ __forceinline__ int64_t xcd_slab(int64_t b, int64_t nblocks, int64_t n) {
-  int64_t per = nblocks >> 3;
-  int64_t i = (b & 7) * per + (b >> 3);
-  return i < n ? i : -1;
-}
-
-// Particle-particle (body-leaf) term: softened acceleration toward source j
-// and potential -m_j / r~, r~^2 = |x_j - x_i|^2 + eps^2.
-__device__ __forceinline__ void pp_term(const float4 xi, const float4 sj, float eps2, float& ax,
-                                        float& ay, float& az, float& ph) {
-  const float dx = sj.x - xi.x, dy = sj.y - xi.y, dz = sj.z - xi.z;
-  const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-  const float ri = __builtin_amdgcn_rsqf(r2);
-  const float mri = sj.w * ri;
-  const float mri3 = mri * (ri * ri);
-  ax = fmaf(mri3, dx, ax);
-  ay = fmaf(mri3, dy, ay);
-  az = fmaf(mri3, dz, az);
-  ph -= mri;
-}
-
-// Particle-cell (body-node) term: softened monopole + traceless quadrupole
-// about the cell's centre of mass, R = x_i - com, q = Q R, s = R.q:
-//   phi += -M/r~ - s/(2 r~^5),  a += -M R/r~^3 + q/r~^5 - 5 s R/(2 r~^7).
-// m0 = (com, M), m1 = (Qxx, Qyy, Qzz, Qxy), m2 = (Qxz, Qyz, -, -).
-__device__ __forceinline__ void pc_term(const float4 xi, const float4 m0, const float4 m1,
-                                        const float4 m2, float eps2, float& ax, float& ay,
-                                        float& az, float& ph) {
-  const float dx = xi.x - m0.x, dy = xi.y - m0.y, dz = xi.z - m0.z;
-  const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-  const float ri = __builtin_amdgcn_rsqf(r2);
-  const float ri2 = ri * ri;
-  const float qx = fmaf(m2.x, dz, fmaf(m1.w, dy, m1.x * dx));
-  const float qy = fmaf(m2.y, dz, fmaf(m1.y, dy, m1.w * dx));
-  const float qz = fmaf(m1.z, dz, fmaf(m2.y, dy, m2.x * dx));
-  const float s = fmaf(dz, qz, fmaf(dy, qy, dx * qx));
-  const float u = s * (ri2 * ri2);
-  ph = fmaf(-ri, fmaf(0.5f, u, m0.w), ph);
-  const float ri3 = ri * ri2;
-  const float c1 = -fmaf(2.5f, u, m0.w) * ri3;
-  const float c2 = ri3 * ri2;
-  ax = fmaf(c2, qx, fmaf(c1, dx, ax));
-  ay = fmaf(c2, qy, fmaf(c1, dy, ay));
-  az = fmaf(c2, qz, fmaf(c1, dz, az));
-}
-
-// Neumaier compensated addition of v into (s, c).
-__device__ __forceinline__ void neu_add(float& s, float& c, float v) {
-  const float t = s + v;
-  c += (fabsf(s) >= fabsf(v)) ? ((s - t) + v) : ((v - t) + s);
-  s = t;
-}
-
-struct Sum4 {
-  float s[4], c[4];
-  __device__ void zero() {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) s[k] = c[k] = 0.0f;
-  }
-  template <bool PLAIN>
-  __device__ void fold(float a0, float a1, float a2, float a3) {
-    if (PLAIN) {
-      s[0] += a0;
-      s[1] += a1;
-      s[2] += a2;
-      s[3] += a3;
-    } else {
-      neu_add(s[0], c[0], a0);
-      neu_add(s[1], c[1], a1);
-      neu_add(s[2], c[2], a2);
-      neu_add(s[3], c[3], a3);
-    }
-  }
-};
 
 // Block-wide exclusive scan of one int per thread (256 threads).
 __device__ int block_excl_scan_int(int v, int* sh, int* total) {
@@ -155,7 +83,7 @@ __global__ __launch_bounds__(kThreads) void eval_kernel(DevTree T, WalkBufs B, f
     __syncthreads();
     if (active) {
       float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-      for (int j = slice; j < cnt; j += S) pc_term(xi, sh0[j], sh1[j], sh2[j], eps2, ax, ay, az, ph);
+      strided2(slice, cnt, S, [&](int j) { pc_term(xi, sh0[j], sh1[j], sh2[j], eps2, ax, ay, az, ph); });
       acc4.fold<PLAIN>(ax, ay, az, ph);
     }
     __syncthreads();
@@ -192,7 +120,7 @@ __global__ __launch_bounds__(kThreads) void eval_kernel(DevTree T, WalkBufs B, f
       __syncthreads();
       if (active) {
         float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-        for (int j = slice; j < cnt; j += S) pp_term(xi, sh0[j], eps2, ax, ay, az, ph);
+        strided2(slice, cnt, S, [&](int j) { pp_term(xi, sh0[j], eps2, ax, ay, az, ph); });
         acc4.fold<PLAIN>(ax, ay, az, ph);
       }
       __syncthreads();

@@ -8,7 +8,7 @@
 namespace octgrav {
 
 constexpr int kMaxDepth = 21;   // levels below the root cube (63-bit Morton keys)
-constexpr int kChunk = 64;      // targets per evaluation work item
+constexpr int kChunk = 32;      // targets per evaluation work item
 
 // Host tree (Sec. 2.1), FP64 geometry and moments, FP32 device images.
 struct HostTree {
@@ -42,7 +42,8 @@ struct DevTree {
   const float* part;     // float4 [n]
   const int32_t* perm;   // [n]
   const int32_t* topo;   // int4 [nc]
-  const float* geo;      // float4 [nc]
+  const float* geo;      // float4 [nc]  boundary; the side's sign bit marks leaves
+  const float* wrec;     // float4 x2 [nc] walk record: boundary (as geo) | topo
   const float* mp;       // float4 x3 [nc]
   const int32_t* ginfo;  // int4 [ng]
   const float* gbox;     // float4 x2 [ng]
@@ -59,12 +60,13 @@ struct WalkBufs {
   int64_t cap_c, cap_l;
   int64_t* tot;        // [8]: n_c, n_l, N_pc, N_pp, capacity-overflow, fallback-overflow
   int64_t* blk;        // scan scratch: 2 per scan block
-  int32_t* ovf_list;   // [ng] groups whose LDS frontier overflowed
+  int32_t* ovf_list;   // [max(ng, nw)] groups / work items whose LDS frontier overflowed
   int32_t* ovf_count;  // [1]
   int32_t* gq;         // global frontier queues for the fallback walk
   int64_t gq_cap;      // entries per queue (power of two)
   int32_t gq_waves;    // queues (waves) of the fallback walk
-  int32_t lds_qcap;    // LDS frontier entries used per wave (power of two <= 2048)
+  int32_t lds_qcap;    // cap on the LDS frontier entries used (power of two; test hook)
+  int32_t export_lists;  // fused walk: also write the lists at c_off / l_off
 };
 
 // Kernel launchers (device sources).  mode 0 = count, 1 = write.
@@ -72,6 +74,8 @@ int launch_walk(const DevTree& T, const WalkBufs& B, float theta, int mode, void
 int launch_scan(const DevTree& T, const WalkBufs& B, void* stream);
 int launch_eval(const DevTree& T, const WalkBufs& B, float eps, bool plain, float* acc,
                 float* pot, void* stream);
+int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps, bool plain,
+                     bool do_eval, float* acc, float* pot, void* stream);
 int launch_diag(const DevTree& T, const float* acc, const float* pot, double* part_sums,
                 double* out4, void* stream);
 int64_t scan_scratch_entries(int64_t ng);

@@ -16,44 +16,16 @@
 // sized from the widest tree level, so they cannot overflow.
 #include <hip/hip_runtime.h>
 
+#include "device_common.h"
 #include "octgrav_internal.h"
 
 namespace octgrav {
 namespace {
 
+using namespace dev;
+
 constexpr int kQueueLds = 2048;  // LDS frontier entries per wave (power of two)
 constexpr int kFallbackWaves = 128;
-
-__device__ __forceinline__ int rank_below(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-}
-
-__device__ __forceinline__ int wave_sum(int v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous (Morton-ordered, hence spatially coherent) range of groups so
-// that neighbouring groups share the XCD's L2.
-__device__ __forceinline__ int64_t xcd_slab(int64_t b, int64_t nblocks, int64_t n) {
-  int64_t per = nblocks >> 3;
-  int64_t i = (b & 7) * per + (b >> 3);
-  return i < n ? i : -1;
-}
-
-// Opening test (Sec. 2.2): open iff d2 == 0 or d2 * theta^2 < l^2, where d is
-// the distance from the cell's boundary centre to the group's tight box.
-// FP32, this exact operation order, no contraction: the decision is bit-exact
-// against any IEEE implementation of the same expression.
-__device__ __forceinline__ bool open_cell(float4 gmin, float4 gmax, float4 c, float th2) {
-#pragma clang fp contract(off)
-  float tx = fmaxf(fmaxf(gmin.x - c.x, c.x - gmax.x), 0.0f);
-  float ty = fmaxf(fmaxf(gmin.y - c.y, c.y - gmax.y), 0.0f);
-  float tz = fmaxf(fmaxf(gmin.z - c.z, c.z - gmax.z), 0.0f);
-  float d2 = (tx * tx + ty * ty) + tz * tz;
-  return d2 == 0.0f || d2 * th2 < c.w * c.w;
-}
 
 // One wave walks group g.  MODE 0 counts, MODE 1 writes at the offsets.
 // Q is the frontier storage (LDS, or a volatile global queue in the fallback).
@@ -90,11 +62,14 @@ __device__ void walk_group(const DevTree& T, const WalkBufs& B, int64_t g, float
       const bool valid = (uint32_t)lane < navail;
       const int c = valid ? (int)q[(head + lane) & qmask] : 0;
       const float4 ge = geo[c];
-      const int4 tp = topo[c];
-      const bool op = open_cell(gmin, gmax, ge, th2);
+      const bool op = valid && open_cell(gmin, gmax, ge, th2);
+      // The device boundary side carries the leaf flag in its sign bit; the
+      // test only uses its square.
+      const bool leaf = __float_as_int(ge.w) < 0;
+      const int4 tp = op ? topo[c] : make_int4(0, 0, 0, 0);
       const bool toC = valid && !op;
-      const bool toL = valid && op && tp.y == 0;
-      const bool push = valid && op && tp.y != 0;
+      const bool toL = op && leaf;
+      const bool push = op && !leaf;
       const uint64_t mC = __ballot(toC), mL = __ballot(toL);
       if (MODE == 1) {
         if (toC) B.c_ids[cb + nC + rank_below(mC)] = c;

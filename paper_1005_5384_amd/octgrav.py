@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EHIP, ECAPACITY = 0, -1, -2, -3, -4
 BUILD_HOST_ONLY = 1
 PLAIN_SUM = 1
 TIMED = 2
+TWO_PASS = 4
 
 _lib = None
 
@@ -41,7 +42,8 @@ class TreeView(C.Structure):
 
 EXPORTED = ["octgrav_build_tree", "octgrav_build_tree_ex", "octgrav_forces", "octgrav_forces_ex",
             "octgrav_free", "octgrav_last_error", "octgrav_set_stream", "octgrav_tree_stats",
-            "octgrav_export_tree", "octgrav_lists", "octgrav_diagnostics", "octgrav_last_counts",
+            "octgrav_export_tree", "octgrav_lists", "octgrav_lists_ex", "octgrav_diagnostics",
+            "octgrav_last_counts",
             "octgrav_last_timings"]
 
 
@@ -71,6 +73,8 @@ def lib():
         L.octgrav_tree_stats.argtypes = [vp, C.POINTER(Stats)]
         L.octgrav_export_tree.argtypes = [vp, C.POINTER(TreeView)]
         L.octgrav_lists.argtypes = [vp, f32, vp, vp, vp, vp, C.POINTER(i64), C.POINTER(i64)]
+        L.octgrav_lists_ex.argtypes = [vp, f32, C.c_uint32, vp, vp, vp, vp, C.POINTER(i64),
+                                       C.POINTER(i64)]
         L.octgrav_diagnostics.argtypes = [vp, vp, vp]
         L.octgrav_last_counts.argtypes = [vp, vp]
         L.octgrav_last_timings.argtypes = [vp, vp]
@@ -121,7 +125,8 @@ class Tree:
         import torch
         _check(lib().octgrav_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
-    def forces(self, theta, eps, acc=None, pot=None, plain=False, timed=False, with_pot=True):
+    def forces(self, theta, eps, acc=None, pot=None, plain=False, timed=False, with_pot=True,
+               two_pass=False):
         """(acc [n,3], pot [n]) as float32 torch tensors on the current device."""
         import torch
         if acc is None:
@@ -134,24 +139,26 @@ class Tree:
         if acc.numel() != 3 * self.n or (pot is not None and pot.numel() != self.n):
             raise ValueError("acc must hold n*3 and pot n elements")
         self._bind_stream()
-        flags = (PLAIN_SUM if plain else 0) | (TIMED if timed else 0)
+        flags = (PLAIN_SUM if plain else 0) | (TIMED if timed else 0) | (TWO_PASS if two_pass else 0)
         _check(lib().octgrav_forces_ex(self._h, float(theta), float(eps), C.c_void_p(acc.data_ptr()),
                                        None if pot is None else C.c_void_p(pot.data_ptr()), flags))
         return acc, pot
 
-    def lists(self, theta):
-        """(c_off, c_ids, l_off, l_ids) numpy CSR lists built by the GPU walk."""
+    def lists(self, theta, two_pass=False):
+        """(c_off, c_ids, l_off, l_ids) numpy CSR lists built by the GPU walk
+        (the fused walk of the default force path, or the two-pass write walk)."""
         self._bind_stream()
+        fl = TWO_PASS if two_pass else 0
         nc, nl = C.c_int64(), C.c_int64()
-        _check(lib().octgrav_lists(self._h, float(theta), None, None, None, None,
-                                   C.byref(nc), C.byref(nl)))
+        _check(lib().octgrav_lists_ex(self._h, float(theta), fl, None, None, None, None,
+                                      C.byref(nc), C.byref(nl)))
         ng = self.stats["n_groups"]
         c_off = np.zeros(ng + 1, np.int64)
         l_off = np.zeros(ng + 1, np.int64)
         c_ids = np.zeros(max(1, nc.value), np.int32)
         l_ids = np.zeros(max(1, nl.value), np.int32)
-        _check(lib().octgrav_lists(self._h, float(theta), _ptr(c_off), _ptr(c_ids), _ptr(l_off),
-                                   _ptr(l_ids), C.byref(nc), C.byref(nl)))
+        _check(lib().octgrav_lists_ex(self._h, float(theta), fl, _ptr(c_off), _ptr(c_ids),
+                                      _ptr(l_off), _ptr(l_ids), C.byref(nc), C.byref(nl)))
         return c_off, c_ids[:nc.value], l_off, l_ids[:nl.value]
 
     def export(self):

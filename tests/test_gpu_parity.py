@@ -58,7 +58,9 @@ def _gpu_forces(T, theta, eps, **kw):
 def test_lists_small_variety(n, n_leaf, n_group, seed, theta):
     pos, m = W.plummer(n, seed)
     T = og.Tree(pos, m, n_leaf, n_group)
-    _lists_equal(T.lists(theta), oracle.Tree(pos, m, n_leaf, n_group).lists(theta))
+    ref = oracle.Tree(pos, m, n_leaf, n_group).lists(theta)
+    _lists_equal(T.lists(theta), ref)
+    _lists_equal(T.lists(theta, two_pass=True), ref)
 
 
 @pytest.fixture(scope="module")
@@ -71,7 +73,9 @@ def c1():
 @pytest.mark.parametrize("theta", [0.0, 0.3, 0.5, 0.75, 1.0])
 def test_lists_c1(c1, theta):
     pos, m, w, T, O = c1
-    _lists_equal(T.lists(theta), O.lists(theta))
+    ref = O.lists(theta)
+    _lists_equal(T.lists(theta), ref)
+    _lists_equal(T.lists(theta, two_pass=True), ref)
 
 
 @pytest.fixture(scope="module")
@@ -84,7 +88,9 @@ def c2():
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.75])
 def test_lists_c2_full(c2, theta):
     pos, m, w, T, O = c2
-    _lists_equal(T.lists(theta), O.lists(theta))
+    ref = O.lists(theta)
+    _lists_equal(T.lists(theta), ref)
+    _lists_equal(T.lists(theta, two_pass=True), ref)
 
 
 def test_lists_clumps_full():
@@ -110,29 +116,34 @@ def test_lists_via_fallback_walk(c1):
     finally:
         del os.environ["OCTGRAV_LDS_QUEUE"]
     for theta in (0.3, 0.75):
-        _lists_equal(T.lists(theta), O.lists(theta))
-    a, p = _gpu_forces(T, 0.5, w["eps"])
+        ref = O.lists(theta)
+        _lists_equal(T.lists(theta), ref)
+        _lists_equal(T.lists(theta, two_pass=True), ref)
     ar, pr = O.forces(0.5, w["eps"])
-    _gate(a, p, ar, pr, "fallback walk")
+    for tp in (False, True):
+        a, p = _gpu_forces(T, 0.5, w["eps"], two_pass=tp)
+        _gate(a, p, ar, pr, f"fallback walk two_pass={tp}")
 
 
 # ------------------------------------------------------------------ forces
+@pytest.mark.parametrize("two_pass", [False, True])
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.75])
-def test_forces_c1(c1, theta):
+def test_forces_c1(c1, theta, two_pass):
     pos, m, w, T, O = c1
-    a, p = _gpu_forces(T, theta, w["eps"])
+    a, p = _gpu_forces(T, theta, w["eps"], two_pass=two_pass)
     ar, pr = O.forces(theta, w["eps"])
-    _gate(a, p, ar, pr, f"c1 theta={theta}")
+    _gate(a, p, ar, pr, f"c1 theta={theta} two_pass={two_pass}")
 
 
+@pytest.mark.parametrize("two_pass", [False, True])
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.75])
-def test_forces_c2_sampled(c2, theta):
+def test_forces_c2_sampled(c2, theta, two_pass):
     pos, m, w, T, O = c2
     sel = np.random.default_rng(int(theta * 100)).choice(O.n_groups, 400, replace=False)
-    a, p = _gpu_forces(T, theta, w["eps"])
+    a, p = _gpu_forces(T, theta, w["eps"], two_pass=two_pass)
     ar, pr = O.forces(theta, w["eps"], groups=sel)
     k = ~np.isnan(pr)
-    _gate(a[k], p[k], ar[k], pr[k], f"c2 theta={theta}")
+    _gate(a[k], p[k], ar[k], pr[k], f"c2 theta={theta} two_pass={two_pass}")
     # interaction totals reported by the library equal the oracle's counts
     cnt = O.counts(theta)
     gs = O.export()["topo"][O.export()["groups"], 3]
@@ -176,11 +187,20 @@ def test_diagnostics_fp64(c1):
     assert np.all(np.abs(mom) <= 1e-3 * scale)
 
 
-def test_repeatable_bitwise(c1):
+@pytest.mark.parametrize("two_pass", [False, True])
+def test_repeatable_bitwise(c1, two_pass):
     pos, m, w, T, O = c1
-    a1, p1 = _gpu_forces(T, 0.5, w["eps"])
-    a2, p2 = _gpu_forces(T, 0.5, w["eps"])
+    a1, p1 = _gpu_forces(T, 0.5, w["eps"], two_pass=two_pass)
+    a2, p2 = _gpu_forces(T, 0.5, w["eps"], two_pass=two_pass)
     assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+
+
+def test_fused_and_two_pass_agree(c2):
+    # Same lists, different tile interleaving: results agree to rounding.
+    pos, m, w, T, O = c2
+    a1, p1 = _gpu_forces(T, 0.5, w["eps"])
+    a2, p2 = _gpu_forces(T, 0.5, w["eps"], two_pass=True)
+    assert np.median(oracle.rel_err(a1, a2)) < 1e-6 and np.max(oracle.rel_err(a1, a2)) < 1e-4
 
 
 def test_capacity_regrowth(c1):
@@ -188,8 +208,8 @@ def test_capacity_regrowth(c1):
     # buffers are regrown inside the call and the result is still exact.
     pos, m, w, _, O = c1
     T = og.Tree(pos, m, w["n_leaf"], 64)
-    _gpu_forces(T, 1.0, w["eps"])
-    a, p = _gpu_forces(T, 0.3, w["eps"])
+    _gpu_forces(T, 1.0, w["eps"], two_pass=True)
+    a, p = _gpu_forces(T, 0.3, w["eps"], two_pass=True)
     ar, pr = O.forces(0.3, w["eps"])
     _gate(a, p, ar, pr, "regrowth")
 
@@ -233,10 +253,13 @@ def test_coincident_stacks_and_big_groups():
     assert T.stats["n_work"] > T.stats["n_groups"]
     O = oracle.Tree(pos, m, 8, 64)
     for theta in (0.0, 0.5, 1.0):
-        _lists_equal(T.lists(theta), O.lists(theta))
-        a, p = _gpu_forces(T, theta, 0.02)
+        ref = O.lists(theta)
+        _lists_equal(T.lists(theta), ref)
+        _lists_equal(T.lists(theta, two_pass=True), ref)
         ar, pr = O.forces(theta, 0.02)
-        _gate(a, p, ar, pr, f"coincident theta={theta}")
+        for tp in (False, True):
+            a, p = _gpu_forces(T, theta, 0.02, two_pass=tp)
+            _gate(a, p, ar, pr, f"coincident theta={theta} two_pass={tp}")
 
 
 def test_ragged_sizes_match_oracle():
