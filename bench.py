@@ -72,8 +72,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plummer1m")
     ap.add_argument("--theta", type=float, default=0.5)
-    ap.add_argument("--two-pass", action="store_true",
-                    help="separate count walk / offsets / write walk / evaluation kernels")
+    ap.add_argument("--path", default=None, choices=["two_pass", "fused_block", "fused_wave"],
+                    help="force one implementation path (default: the library's choice for theta)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -100,7 +100,7 @@ def main():
     theta, eps = args.theta, w["eps"]
 
     for _ in range(args.warmup):
-        T.forces(theta, eps, acc=acc, pot=pot, timed=True, two_pass=args.two_pass)
+        T.forces(theta, eps, acc=acc, pot=pot, timed=True, path=args.path)
     torch.cuda.synchronize()
     log("bench: warmup done")
 
@@ -108,7 +108,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        T.forces(theta, eps, acc=acc, pot=pot, timed=True, two_pass=args.two_pass)
+        T.forces(theta, eps, acc=acc, pot=pot, timed=True, path=args.path)
         phases.append(T.last_timings())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -137,9 +137,9 @@ def main():
         "config": {"workload": args.workload, "n": n, "distribution": w["gen"], "theta": theta,
                    "eps": eps, "n_leaf": w["n_leaf"], "n_group": 64, "mac": "theta",
                    "accumulation": "compensated",
-                   "path": "two-pass" if args.two_pass else "fused walk+evaluation"},
+                   "path": args.path or "default"},
         "roofline": {"bound": "alu",
-                     "kernel": "eval_kernel" if args.two_pass else "walk_eval_kernel (walk + evaluation)",
+                     "kernel": "evaluation phase (walk included for fused paths)",
                      "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,

@@ -47,8 +47,14 @@ extern "C" {
 /* octgrav_forces_ex flags */
 #define OCTGRAV_PLAIN_SUM 1u /* plain FP32 accumulation instead of compensated */
 #define OCTGRAV_TIMED 2u     /* record HIP events around each kernel phase */
-#define OCTGRAV_TWO_PASS 4u  /* separate count walk, offsets, write walk and evaluation kernels
-                                (the paper's structure) instead of the fused walk+evaluation */
+/* Path selection (at most one; none = chosen from theta, see octgrav_forces):
+ * OCTGRAV_TWO_PASS    count walk, offsets, write walk and evaluation kernels (the paper's
+ *                     structure), pipelined over batches of groups on two streams;
+ * OCTGRAV_FUSED_BLOCK one 256-thread block per group walks and evaluates (lists stay in LDS);
+ * OCTGRAV_FUSED_WAVE  one 64-lane wave per group walks and evaluates. */
+#define OCTGRAV_TWO_PASS 4u
+#define OCTGRAV_FUSED_BLOCK 8u
+#define OCTGRAV_FUSED_WAVE 16u
 
 typedef struct octgrav_tree octgrav_tree;
 
@@ -107,10 +113,12 @@ octgrav_tree* octgrav_build_tree_ex(const float* pos, const float* mass, int64_t
  *   acc    device, n x 3 FP32, caller's order (written)
  *   pot    device, n FP32, caller's order (written), or NULL
  * Runs on the handle's stream and returns once the results are complete on it.
+ * All paths evaluate the same lists; the default picks the fastest measured
+ * one for theta (the fused block walk below 0.4, the fused wave walk above).
  */
 int octgrav_forces(octgrav_tree* t, float theta, float eps, float* acc, float* pot);
 
-/* As octgrav_forces with OCTGRAV_PLAIN_SUM / OCTGRAV_TIMED flags. */
+/* As octgrav_forces with OCTGRAV_PLAIN_SUM / OCTGRAV_TIMED and path flags. */
 int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float* pot,
                       uint32_t flags);
 
@@ -135,17 +143,17 @@ int octgrav_export_tree(const octgrav_tree* t, const octgrav_tree_view* v);
  * Interaction lists of every group at opening angle theta, built by the GPU
  * walk (Sec. 2.2) and copied to the host in CSR form over groups; ids are
  * cell ids in ascending order.  Sizes and offsets come from the count walk
- * and the device prefix sum; the entries are written by the same walk the
- * default force path runs (the fused walk+evaluation, with evaluation
- * skipped).  Two-call pattern: with c_off/c_ids/l_off/l_ids NULL only *n_c
+ * and the device prefix sum; the entries are written by the walk of the path
+ * the same flags select in octgrav_forces_ex (the fused kernels run with
+ * their evaluation skipped).  Two-call pattern: with c_off/c_ids/l_off/l_ids NULL only *n_c
  * and *n_l (total entries) are set; otherwise c_off and l_off hold
  * n_groups+1 int64 each and c_ids/l_ids at least *n_c / *n_l int32 entries.
  */
 int octgrav_lists(octgrav_tree* t, float theta, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
                   int32_t* l_ids, int64_t* n_c, int64_t* n_l);
 
-/* As octgrav_lists; flags OCTGRAV_TWO_PASS takes the entries from the
- * separate write walk instead. */
+/* As octgrav_lists with a path flag (OCTGRAV_TWO_PASS, OCTGRAV_FUSED_BLOCK,
+ * OCTGRAV_FUSED_WAVE; none = the default path for theta). */
 int octgrav_lists_ex(octgrav_tree* t, float theta, uint32_t flags, int64_t* c_off, int32_t* c_ids,
                      int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l);
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -36,6 +37,15 @@ bool alloc_fault() {
   return v && v[0] == '1';
 }
 
+// OCTGRAV_DEBUG=1 traces each force call's path decisions on stderr.
+bool debug_trace() {
+  static const bool on = [] {
+    const char* v = std::getenv("OCTGRAV_DEBUG");
+    return v && v[0] == '1';
+  }();
+  return on;
+}
+
 // Set by OCTGRAV_LDS_QUEUE=<power of two> (test-only): caps the walks' LDS
 // frontier queues so that groups overflow into the global-memory fallback
 // walks.  Unset, the kernels use their full queues.
@@ -61,11 +71,21 @@ struct octgrav_tree {
   bool counts_valid = false;
   hipEvent_t ev[6] = {};
   double timings[6] = {0, 0, 0, 0, 0, 0};
+  // Pipelined two-pass path: a second stream for the evaluation of batch b
+  // while the walks of batch b+1 run on the handle's stream.
+  static constexpr int kBatches = 8;
+  hipStream_t eval_stream = nullptr;
+  hipEvent_t bev[kBatches + 2] = {};
+  std::vector<int64_t> gwork;  // [ng+1] first work item of each group
+  int64_t slot_c = 0, slot_l = 0;  // per-group list slots of the pipelined path (0 = unsized)
 
   ~octgrav_tree() {
     for (void* p : allocs) hipFree(p);
     for (hipEvent_t e : ev)
       if (e) hipEventDestroy(e);
+    for (hipEvent_t e : bev)
+      if (e) hipEventDestroy(e);
+    if (eval_stream) hipStreamDestroy(eval_stream);
   }
 
   int dalloc(void** p, size_t bytes) {
@@ -155,6 +175,13 @@ struct octgrav_tree {
     d_diag = (double*)p;
     for (hipEvent_t& e : ev)
       if (hipEventCreate(&e) != hipSuccess) return fail(OCTGRAV_EHIP, "hipEventCreate failed");
+    for (hipEvent_t& e : bev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        return fail(OCTGRAV_EHIP, "hipEventCreate failed");
+    if (hipStreamCreateWithFlags(&eval_stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(OCTGRAV_EHIP, "hipStreamCreate failed");
+    gwork.assign(ng + 1, nw);
+    for (int64_t w = nw - 1; w >= 0; --w) gwork[h.work[2 * w]] = w;
     dev = true;
     return OCTGRAV_OK;
   }
@@ -189,6 +216,43 @@ struct octgrav_tree {
         hipStreamSynchronize(stream) != hipSuccess)
       return fail(OCTGRAV_EHIP, std::string("device error: ") + hipGetErrorString(hipGetLastError()));
     return OCTGRAV_OK;
+  }
+
+  // Two-pass path, pipelined over batches of groups: on the handle's stream
+  // each batch's count walk, offsets and write walk; on eval_stream its
+  // evaluation, which waits only for that batch's lists.  Needs list buffers
+  // sized by an earlier call; a group whose lists do not fit is skipped and
+  // reported through the totals, and the caller redoes the call.
+  int two_pass_pipelined(float theta, float eps, bool plain, float* acc, float* pot) {
+    const int64_t ng = h.n_groups();
+    const int nb = (int)std::min<int64_t>(kBatches, std::max<int64_t>(1, ng / 256));
+    WalkBufs ws = wb;  // slotted lists: no offsets scan between the walk and the evaluation
+    ws.slot_c = slot_c;
+    ws.slot_l = slot_l;
+    hipEventRecord(bev[kBatches], stream);
+    hipStreamWaitEvent(eval_stream, bev[kBatches], 0);
+    for (int b = 0; b < nb; ++b) {
+      const int64_t g0 = ng * b / nb, g1 = ng * (b + 1) / nb;
+      if (launch_walk(dt, ws, theta, 2, stream, g0, g1 - g0, b == 0))
+        return fail(OCTGRAV_EHIP, "walk launch failed");
+      hipEventRecord(bev[b], stream);
+      hipStreamWaitEvent(eval_stream, bev[b], 0);
+      if (launch_eval(dt, ws, eps, plain, acc, pot, eval_stream, gwork[g0], gwork[g1] - gwork[g0]))
+        return fail(OCTGRAV_EHIP, "evaluation launch failed");
+    }
+    if (launch_totals(dt, ws, stream)) return fail(OCTGRAV_EHIP, "totals launch failed");
+    hipEventRecord(bev[kBatches + 1], eval_stream);
+    hipStreamWaitEvent(stream, bev[kBatches + 1], 0);
+    return OCTGRAV_OK;
+  }
+
+  // Slot sizes for the next pipelined call from the longest lists of this
+  // one (tot[6], tot[7]), with headroom; the buffers are grown to match.
+  int size_slots(const int64_t* tot) {
+    const int64_t ng = h.n_groups();
+    slot_c = (tot[6] + tot[6] / 4 + 63) / 64 * 64 + 64;
+    slot_l = (tot[7] + tot[7] / 4 + 63) / 64 * 64 + 64;
+    return reserve_lists(std::max(tot[0], ng * slot_c), std::max(tot[1], ng * slot_l));
   }
 
   // Count walk + offsets, then sizes the lists (a host read-back only when
@@ -293,6 +357,28 @@ int octgrav_export_tree(const octgrav_tree* t, const octgrav_tree_view* v) {
   return OCTGRAV_OK;
 }
 
+enum class Path { TwoPass, FusedBlock, FusedWave };
+
+// Path of a call: an explicit flag, else the fastest measured for theta on
+// 2^20 Plummer spheres (ms at theta 0.3 / 0.5 / 0.75: fused wave 16.0 / 3.10 /
+// 1.23, fused block 10.9 / 3.27 / 1.72, two-pass 11.9 / 3.44 / 1.55).  The
+// wave variant's 4096-entry LDS queue for small angles limits it to a few
+// walks per CU, where the block variant shares one queue among four waves.
+static Path choose_path(uint32_t flags, float theta) {
+  if (flags & OCTGRAV_TWO_PASS) return Path::TwoPass;
+  if (flags & OCTGRAV_FUSED_BLOCK) return Path::FusedBlock;
+  if (flags & OCTGRAV_FUSED_WAVE) return Path::FusedWave;
+  return theta < 0.4f ? Path::FusedBlock : Path::FusedWave;
+}
+
+static int launch_fused(const octgrav_tree* t, Path p, float theta, float eps, bool plain,
+                        bool do_eval, float* acc, float* pot) {
+  int rc = p == Path::FusedWave
+               ? launch_walk_eval(t->dt, t->wb, theta, eps, plain, do_eval, acc, pot, t->stream)
+               : launch_walk_eval_block(t->dt, t->wb, theta, eps, plain, do_eval, acc, pot, t->stream);
+  return rc ? rc : launch_totals(t->dt, t->wb, t->stream);
+}
+
 static int check_theta(const octgrav_tree* t, float theta) {
   if (!t) return fail(OCTGRAV_EINVAL, "NULL handle");
   if (!t->dev) return fail(OCTGRAV_EINVAL, "tree was built host-only");
@@ -311,37 +397,53 @@ int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float
     t->counts_valid = false;
     t->have_diag = false;
     int64_t tot[8];
-    if (!(flags & OCTGRAV_TWO_PASS)) {
-      // Fused walk + evaluation: no lists in memory, no host round trip.
-      t->wb.export_lists = 0;
+    const Path path = choose_path(flags, theta);
+    for (int attempt = 0; attempt < 2; ++attempt) {
       if (timed) {
         for (int k = 0; k < 4; ++k) hipEventRecord(t->ev[k], t->stream);
       }
-      if (launch_walk_eval(t->dt, t->wb, theta, eps, plain, true, acc, pot, t->stream))
-        return fail(OCTGRAV_EHIP, "walk+evaluation launch failed");
-      if (timed) hipEventRecord(t->ev[4], t->stream);
-    } else {
-      if (int rc = t->lists_on_device(theta, timed)) return rc;
-      for (int attempt = 0;; ++attempt) {
+      if (path != Path::TwoPass) {
+        // Fused walk + evaluation: no lists in memory, no host round trip.
+        t->wb.export_lists = 0;
+        if (launch_fused(t, path, theta, eps, plain, true, acc, pot))
+          return fail(OCTGRAV_EHIP, "walk+evaluation launch failed");
+      } else if (t->slot_c > 0 && attempt == 0) {
+        if (int rc = t->two_pass_pipelined(theta, eps, plain, acc, pot)) return rc;
+      } else {
+        // First call on this handle (the count walk sizes the list buffers),
+        // or a retry after the lists outgrew them.
+        if (int rc = t->lists_on_device(theta, timed)) return rc;
         if (launch_eval(t->dt, t->wb, eps, plain, acc, pot, t->stream))
           return fail(OCTGRAV_EHIP, "evaluation launch failed");
-        if (timed) hipEventRecord(t->ev[4], t->stream);
-        if (int rc = t->read_tot(tot)) return rc;
-        if (tot[0] <= t->wb.cap_c && tot[1] <= t->wb.cap_l) break;
-        if (attempt == 1) return fail(OCTGRAV_ECAPACITY, "list capacity still exceeded after retry");
-        // Lists outgrew the buffers of an earlier call: grow and rewrite.
-        if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
-        if (timed) hipEventRecord(t->ev[2], t->stream);
-        if (launch_walk(t->dt, t->wb, theta, 1, t->stream))
-          return fail(OCTGRAV_EHIP, "write walk launch failed");
-        if (timed) hipEventRecord(t->ev[3], t->stream);
       }
+      if (timed) hipEventRecord(t->ev[4], t->stream);
+      if (launch_diag(t->dt, acc, pot, t->d_diag_part, t->d_diag, t->stream))
+        return fail(OCTGRAV_EHIP, "diagnostics launch failed");
+      if (timed) hipEventRecord(t->ev[5], t->stream);
+      if (int rc = t->read_tot(tot)) return rc;
+      if (debug_trace())
+        std::fprintf(stderr,
+                     "octgrav: attempt %d path %d slots %lld/%lld cap %lld/%lld tot %lld %lld %lld "
+                     "%lld %lld %lld %lld %lld\n",
+                     attempt, (int)path, (long long)t->slot_c, (long long)t->slot_l,
+                     (long long)t->wb.cap_c, (long long)t->wb.cap_l, (long long)tot[0],
+                     (long long)tot[1], (long long)tot[2], (long long)tot[3], (long long)tot[4],
+                     (long long)tot[5], (long long)tot[6], (long long)tot[7]);
+      if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+      if (path != Path::TwoPass) break;
+      const bool slotted = t->slot_c > 0 && attempt == 0;
+      const bool fits = slotted ? !tot[4] : (tot[0] <= t->wb.cap_c && tot[1] <= t->wb.cap_l);
+      if (fits) {
+        if (!slotted)
+          if (int rc = t->size_slots(tot)) return rc;
+        break;
+      }
+      if (attempt == 1) return fail(OCTGRAV_ECAPACITY, "list capacity still exceeded after retry");
+      // Slotted lists outgrew their slots: redo exactly (count walk, offsets,
+      // write walk), which also resizes the slots for later calls.
+      if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
+      t->slot_c = t->slot_l = 0;
     }
-    if (launch_diag(t->dt, acc, pot, t->d_diag_part, t->d_diag, t->stream))
-      return fail(OCTGRAV_EHIP, "diagnostics launch failed");
-    if (timed) hipEventRecord(t->ev[5], t->stream);
-    if (int rc = t->read_tot(tot)) return rc;
-    if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
     t->counts_valid = true;
     t->have_diag = true;
     if (timed) {
@@ -382,11 +484,12 @@ int octgrav_lists_ex(octgrav_tree* t, float theta, uint32_t flags, int64_t* c_of
     if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
     *n_c = tot[0];
     *n_l = tot[1];
-    if (flags & OCTGRAV_TWO_PASS) {
+    const Path path = choose_path(flags, theta);
+    if (path == Path::TwoPass) {
       if (launch_walk(t->dt, t->wb, theta, 1, t->stream)) return fail(OCTGRAV_EHIP, "write walk launch failed");
     } else {
       t->wb.export_lists = 1;
-      int rc = launch_walk_eval(t->dt, t->wb, theta, 1.0f, false, false, nullptr, nullptr, t->stream);
+      int rc = launch_fused(t, path, theta, 1.0f, false, false, nullptr, nullptr);
       t->wb.export_lists = 0;
       if (rc) return fail(OCTGRAV_EHIP, "walk (export) launch failed");
     }

@@ -14,6 +14,9 @@
 // in plain FP32 and folds it into a Neumaier-compensated (sum, carry) pair.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdlib>
+
 #include "device_common.h"
 #include "octgrav_internal.h"
 
@@ -42,21 +45,41 @@ __device__ int block_excl_scan_int(int v, int* sh, int* total) {
   return incl - v;
 }
 
+struct EvalShared {
+  float4 buf[3 * kTile];
+  int pre[kTile + 1], first[kTile], scan[kThreads];
+};
+
 template <bool PLAIN>
-__global__ __launch_bounds__(kThreads) void eval_kernel(DevTree T, WalkBufs B, float eps2,
-                                                        float* __restrict__ acc,
-                                                        float* __restrict__ pot) {
-  __shared__ float4 shbuf[3 * kTile];
+__device__ void eval_item(const DevTree& T, const WalkBufs& B, EvalShared& es, float eps2,
+                          float* __restrict__ acc, float* __restrict__ pot, int64_t w) {
+  float4* shbuf = es.buf;
   float4* sh0 = shbuf;
   float4* sh1 = shbuf + kTile;
   float4* sh2 = shbuf + 2 * kTile;
-  __shared__ int sh_pre[kTile + 1], sh_first[kTile], sh_scan[kThreads];
-  const int64_t w = xcd_slab(blockIdx.x, gridDim.x, T.nw);
-  if (w < 0) return;
-  if (B.tot[0] > B.cap_c || B.tot[1] > B.cap_l) return;  // lists incomplete: the host retries
+  int* sh_pre = es.pre;
+  int* sh_first = es.first;
+  int* sh_scan = es.scan;
   const int tid = threadIdx.x;
   const int2 wk = reinterpret_cast<const int2*>(T.work)[w];
   const int64_t g = wk.x;
+  // List ranges: CSR offsets, or per-group slots.  Lists that did not fit
+  // are incomplete: skip them, the host redoes the call.
+  int64_t c0, c1, l0, l1;
+  if (B.slot_c > 0) {
+    const int4 cn = reinterpret_cast<const int4*>(B.cnt)[g];
+    if (cn.x > B.slot_c || cn.y > B.slot_l) return;  // uniform per block
+    c0 = g * B.slot_c;
+    c1 = c0 + cn.x;
+    l0 = g * B.slot_l;
+    l1 = l0 + cn.y;
+  } else {
+    c0 = B.c_off[g];
+    c1 = B.c_off[g + 1];
+    l0 = B.l_off[g];
+    l1 = B.l_off[g + 1];
+    if (c1 > B.cap_c || l1 > B.cap_l) return;  // uniform per block
+  }
   const int4 gi = reinterpret_cast<const int4*>(T.ginfo)[g];
   const int first = gi.x + wk.y;
   const int nt = min(kChunk, gi.y - wk.y);
@@ -71,7 +94,6 @@ __global__ __launch_bounds__(kThreads) void eval_kernel(DevTree T, WalkBufs B, f
   acc4.zero();
 
   // Cell list: tiles of up to 256 cells' moments staged in LDS.
-  const int64_t c0 = B.c_off[g], c1 = B.c_off[g + 1];
   for (int64_t base = c0; base < c1; base += kTile) {
     const int cnt = (int)min((int64_t)kTile, c1 - base);
     if (tid < cnt) {
@@ -91,7 +113,6 @@ __global__ __launch_bounds__(kThreads) void eval_kernel(DevTree T, WalkBufs B, f
 
   // Leaf list: windows of up to 256 leaves; their particles, flattened in
   // list order, are staged in LDS tiles of 256.
-  const int64_t l0 = B.l_off[g], l1 = B.l_off[g + 1];
   for (int64_t lb = l0; lb < l1; lb += kTile) {
     const int lc = (int)min((int64_t)kTile, l1 - lb);
     int ln = 0;
@@ -163,6 +184,22 @@ __global__ __launch_bounds__(kThreads) void eval_kernel(DevTree T, WalkBufs B, f
     acc[3 * (int64_t)o + 2] = s[2] + c[2];
     if (pot) pot[o] = s[3] + c[3];
   }
+  __syncthreads();
+}
+
+// Blocks take the work items [w0, w0 + nw) in XCD slabs; with fewer blocks
+// than items each block strides through its slab (grid is a multiple of 8).
+template <bool PLAIN>
+__global__ __launch_bounds__(kThreads) void eval_kernel(DevTree T, WalkBufs B, float eps2,
+                                                        float* __restrict__ acc,
+                                                        float* __restrict__ pot, int64_t w0,
+                                                        int64_t nw) {
+  __shared__ EvalShared es;
+  const int64_t nv = ((nw + 7) / 8) * 8;
+  for (int64_t v = blockIdx.x; v < nv; v += gridDim.x) {
+    const int64_t wi = xcd_slab(v, nv, nw);
+    if (wi >= 0) eval_item<PLAIN>(T, B, es, eps2, acc, pot, w0 + wi);
+  }
 }
 
 // ------------------------------------------------------------ diagnostics
@@ -213,12 +250,14 @@ __global__ __launch_bounds__(256) void diag_final_kernel(const double* part_sums
 }  // namespace
 
 int launch_eval(const DevTree& T, const WalkBufs& B, float eps, bool plain, float* acc,
-                float* pot, void* stream) {
+                float* pot, void* stream, int64_t w0, int64_t nw) {
   hipStream_t s = (hipStream_t)stream;
   const float eps2 = eps * eps;
-  const int64_t grid = ((T.nw + 7) / 8) * 8;
-  if (plain) eval_kernel<true><<<grid, kThreads, 0, s>>>(T, B, eps2, acc, pot);
-  else eval_kernel<false><<<grid, kThreads, 0, s>>>(T, B, eps2, acc, pot);
+  if (nw < 0) nw = T.nw - w0;
+  const int64_t grid = ((nw + 7) / 8) * 8;
+  if (grid == 0) return 0;
+  if (plain) eval_kernel<true><<<grid, kThreads, 0, s>>>(T, B, eps2, acc, pot, w0, nw);
+  else eval_kernel<false><<<grid, kThreads, 0, s>>>(T, B, eps2, acc, pot, w0, nw);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -67,15 +67,25 @@ struct WalkBufs {
   int32_t gq_waves;    // queues (waves) of the fallback walk
   int32_t lds_qcap;    // cap on the LDS frontier entries used (power of two; test hook)
   int32_t export_lists;  // fused walk: also write the lists at c_off / l_off
+  // Slotted lists (walk mode 2, > 0): group g's lists start at g * slot_c /
+  // g * slot_l and their lengths are cnt[g].x / .y; 0 = CSR offsets.
+  int64_t slot_c, slot_l;
 };
 
-// Kernel launchers (device sources).  mode 0 = count, 1 = write.
-int launch_walk(const DevTree& T, const WalkBufs& B, float theta, int mode, void* stream);
-int launch_scan(const DevTree& T, const WalkBufs& B, void* stream);
+// Kernel launchers (device sources).  mode 0 = count, 1 = write at the
+// offsets, 2 = count and write into per-group slots.  Ranges
+// are [g0, g0 + ng) groups / [w0, w0 + nw) work items (ng, nw < 0: to the end).
+int launch_walk(const DevTree& T, const WalkBufs& B, float theta, int mode, void* stream,
+                int64_t g0 = 0, int64_t ng = -1, bool init = true);
+int launch_scan(const DevTree& T, const WalkBufs& B, void* stream, int64_t g0 = 0, int64_t ng = -1);
+// Interaction totals and longest lists from the per-group counts.
+int launch_totals(const DevTree& T, const WalkBufs& B, void* stream, int64_t g0 = 0, int64_t ng = -1);
 int launch_eval(const DevTree& T, const WalkBufs& B, float eps, bool plain, float* acc,
-                float* pot, void* stream);
+                float* pot, void* stream, int64_t w0 = 0, int64_t nw = -1);
 int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps, bool plain,
                      bool do_eval, float* acc, float* pot, void* stream);
+int launch_walk_eval_block(const DevTree& T, const WalkBufs& B, float theta, float eps, bool plain,
+                           bool do_eval, float* acc, float* pot, void* stream);
 int launch_diag(const DevTree& T, const float* acc, const float* pot, double* part_sums,
                 double* out4, void* stream);
 int64_t scan_scratch_entries(int64_t ng);

@@ -239,15 +239,8 @@ __device__ bool walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int6
     lhead += n;
   }
 
-  if (lane == 0) {
-    unsigned long long* tot = reinterpret_cast<unsigned long long*>(B.tot);
-    if (wk.y == 0) {
-      atomicAdd(&tot[0], (unsigned long long)ctail);
-      atomicAdd(&tot[1], (unsigned long long)ltail);
-    }
-    atomicAdd(&tot[2], (unsigned long long)ctail * it.nt);
-    atomicAdd(&tot[3], (unsigned long long)it.nsrc * it.nt);
-  }
+  if (lane == 0 && wk.y == 0)  // per-group counts; the totals are reduced afterwards
+    reinterpret_cast<int4*>(B.cnt)[g] = make_int4((int)ctail, (int)ltail, (int)it.nsrc, 0);
   if (!do_eval) return true;
 
   // Combine the slices of each target in slice order.

@@ -19,6 +19,9 @@ BUILD_HOST_ONLY = 1
 PLAIN_SUM = 1
 TIMED = 2
 TWO_PASS = 4
+FUSED_BLOCK = 8
+FUSED_WAVE = 16
+PATHS = {None: 0, "two_pass": TWO_PASS, "fused_block": FUSED_BLOCK, "fused_wave": FUSED_WAVE}
 
 _lib = None
 
@@ -126,7 +129,7 @@ class Tree:
         _check(lib().octgrav_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
     def forces(self, theta, eps, acc=None, pot=None, plain=False, timed=False, with_pot=True,
-               two_pass=False):
+               two_pass=False, path=None):
         """(acc [n,3], pot [n]) as float32 torch tensors on the current device."""
         import torch
         if acc is None:
@@ -140,15 +143,16 @@ class Tree:
             raise ValueError("acc must hold n*3 and pot n elements")
         self._bind_stream()
         flags = (PLAIN_SUM if plain else 0) | (TIMED if timed else 0) | (TWO_PASS if two_pass else 0)
+        flags |= PATHS[path]
         _check(lib().octgrav_forces_ex(self._h, float(theta), float(eps), C.c_void_p(acc.data_ptr()),
                                        None if pot is None else C.c_void_p(pot.data_ptr()), flags))
         return acc, pot
 
-    def lists(self, theta, two_pass=False):
-        """(c_off, c_ids, l_off, l_ids) numpy CSR lists built by the GPU walk
-        (the fused walk of the default force path, or the two-pass write walk)."""
+    def lists(self, theta, two_pass=False, path=None):
+        """(c_off, c_ids, l_off, l_ids) numpy CSR lists built by the GPU walk of
+        the selected path (default: the force path's default for theta)."""
         self._bind_stream()
-        fl = TWO_PASS if two_pass else 0
+        fl = (TWO_PASS if two_pass else 0) | PATHS[path]
         nc, nl = C.c_int64(), C.c_int64()
         _check(lib().octgrav_lists_ex(self._h, float(theta), fl, None, None, None, None,
                                       C.byref(nc), C.byref(nl)))

@@ -24,6 +24,15 @@ def _torch():
     return torch
 
 
+PATHS = ("two_pass", "fused_block", "fused_wave")
+
+
+def _lists_all_paths(T, theta, ref):
+    _lists_equal(T.lists(theta), ref)
+    for p in PATHS:
+        _lists_equal(T.lists(theta, path=p), ref)
+
+
 def _lists_equal(gpu, orc):
     names = ("c_off", "c_ids", "l_off", "l_ids")
     for name, a, b in zip(names, gpu, orc):
@@ -59,8 +68,7 @@ def test_lists_small_variety(n, n_leaf, n_group, seed, theta):
     pos, m = W.plummer(n, seed)
     T = og.Tree(pos, m, n_leaf, n_group)
     ref = oracle.Tree(pos, m, n_leaf, n_group).lists(theta)
-    _lists_equal(T.lists(theta), ref)
-    _lists_equal(T.lists(theta, two_pass=True), ref)
+    _lists_all_paths(T, theta, ref)
 
 
 @pytest.fixture(scope="module")
@@ -73,9 +81,7 @@ def c1():
 @pytest.mark.parametrize("theta", [0.0, 0.3, 0.5, 0.75, 1.0])
 def test_lists_c1(c1, theta):
     pos, m, w, T, O = c1
-    ref = O.lists(theta)
-    _lists_equal(T.lists(theta), ref)
-    _lists_equal(T.lists(theta, two_pass=True), ref)
+    _lists_all_paths(T, theta, O.lists(theta))
 
 
 @pytest.fixture(scope="module")
@@ -88,9 +94,7 @@ def c2():
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.75])
 def test_lists_c2_full(c2, theta):
     pos, m, w, T, O = c2
-    ref = O.lists(theta)
-    _lists_equal(T.lists(theta), ref)
-    _lists_equal(T.lists(theta, two_pass=True), ref)
+    _lists_all_paths(T, theta, O.lists(theta))
 
 
 def test_lists_clumps_full():
@@ -116,34 +120,32 @@ def test_lists_via_fallback_walk(c1):
     finally:
         del os.environ["OCTGRAV_LDS_QUEUE"]
     for theta in (0.3, 0.75):
-        ref = O.lists(theta)
-        _lists_equal(T.lists(theta), ref)
-        _lists_equal(T.lists(theta, two_pass=True), ref)
+        _lists_all_paths(T, theta, O.lists(theta))
     ar, pr = O.forces(0.5, w["eps"])
-    for tp in (False, True):
-        a, p = _gpu_forces(T, 0.5, w["eps"], two_pass=tp)
-        _gate(a, p, ar, pr, f"fallback walk two_pass={tp}")
+    for p_ in PATHS:
+        a, p = _gpu_forces(T, 0.5, w["eps"], path=p_)
+        _gate(a, p, ar, pr, f"fallback walk path={p_}")
 
 
 # ------------------------------------------------------------------ forces
-@pytest.mark.parametrize("two_pass", [False, True])
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.75])
-def test_forces_c1(c1, theta, two_pass):
+def test_forces_c1(c1, theta, path):
     pos, m, w, T, O = c1
-    a, p = _gpu_forces(T, theta, w["eps"], two_pass=two_pass)
+    a, p = _gpu_forces(T, theta, w["eps"], path=path)
     ar, pr = O.forces(theta, w["eps"])
-    _gate(a, p, ar, pr, f"c1 theta={theta} two_pass={two_pass}")
+    _gate(a, p, ar, pr, f"c1 theta={theta} path={path}")
 
 
-@pytest.mark.parametrize("two_pass", [False, True])
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.75])
-def test_forces_c2_sampled(c2, theta, two_pass):
+def test_forces_c2_sampled(c2, theta, path):
     pos, m, w, T, O = c2
     sel = np.random.default_rng(int(theta * 100)).choice(O.n_groups, 400, replace=False)
-    a, p = _gpu_forces(T, theta, w["eps"], two_pass=two_pass)
+    a, p = _gpu_forces(T, theta, w["eps"], path=path)
     ar, pr = O.forces(theta, w["eps"], groups=sel)
     k = ~np.isnan(pr)
-    _gate(a[k], p[k], ar[k], pr[k], f"c2 theta={theta} two_pass={two_pass}")
+    _gate(a[k], p[k], ar[k], pr[k], f"c2 theta={theta} path={path}")
     # interaction totals reported by the library equal the oracle's counts
     cnt = O.counts(theta)
     gs = O.export()["topo"][O.export()["groups"], 3]
@@ -187,20 +189,22 @@ def test_diagnostics_fp64(c1):
     assert np.all(np.abs(mom) <= 1e-3 * scale)
 
 
-@pytest.mark.parametrize("two_pass", [False, True])
-def test_repeatable_bitwise(c1, two_pass):
+@pytest.mark.parametrize("path", PATHS)
+def test_repeatable_bitwise(c1, path):
     pos, m, w, T, O = c1
-    a1, p1 = _gpu_forces(T, 0.5, w["eps"], two_pass=two_pass)
-    a2, p2 = _gpu_forces(T, 0.5, w["eps"], two_pass=two_pass)
+    a1, p1 = _gpu_forces(T, 0.5, w["eps"], path=path)
+    a2, p2 = _gpu_forces(T, 0.5, w["eps"], path=path)
     assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
 
 
-def test_fused_and_two_pass_agree(c2):
+def test_paths_agree(c2):
     # Same lists, different tile interleaving: results agree to rounding.
     pos, m, w, T, O = c2
-    a1, p1 = _gpu_forces(T, 0.5, w["eps"])
-    a2, p2 = _gpu_forces(T, 0.5, w["eps"], two_pass=True)
-    assert np.median(oracle.rel_err(a1, a2)) < 1e-6 and np.max(oracle.rel_err(a1, a2)) < 1e-4
+    ref, _ = _gpu_forces(T, 0.5, w["eps"], path="two_pass")
+    for p_ in ("fused_block", "fused_wave"):
+        a, _ = _gpu_forces(T, 0.5, w["eps"], path=p_)
+        e = oracle.rel_err(a, ref)
+        assert np.median(e) < 1e-6 and e.max() < 1e-4
 
 
 def test_capacity_regrowth(c1):
@@ -253,13 +257,11 @@ def test_coincident_stacks_and_big_groups():
     assert T.stats["n_work"] > T.stats["n_groups"]
     O = oracle.Tree(pos, m, 8, 64)
     for theta in (0.0, 0.5, 1.0):
-        ref = O.lists(theta)
-        _lists_equal(T.lists(theta), ref)
-        _lists_equal(T.lists(theta, two_pass=True), ref)
+        _lists_all_paths(T, theta, O.lists(theta))
         ar, pr = O.forces(theta, 0.02)
-        for tp in (False, True):
-            a, p = _gpu_forces(T, theta, 0.02, two_pass=tp)
-            _gate(a, p, ar, pr, f"coincident theta={theta} two_pass={tp}")
+        for p_ in PATHS:
+            a, p = _gpu_forces(T, theta, 0.02, path=p_)
+            _gate(a, p, ar, pr, f"coincident theta={theta} path={p_}")
 
 
 def test_ragged_sizes_match_oracle():
