@@ -46,6 +46,19 @@ def lib():
         L.orc_counts.argtypes = [vp, C.c_float, _i64p]
         L.orc_diagnostics.argtypes = [_f32p, _f64p, vp, C.c_int64, _f64p]
         L.orc_num_threads.restype = C.c_int
+        L.orc_mlp_params.restype = C.c_int
+        L.orc_mac_features.argtypes = [vp, _i32p, _i32p, C.c_int64, _f32p]
+        L.orc_mac_band.argtypes = [vp, C.c_float, C.c_float, vp, C.c_int64, vp, vp, C.c_int64,
+                                   C.POINTER(C.c_int64)]
+        L.orc_mac_labels.argtypes = [vp, _f64p, C.c_float, _i32p, _i32p, C.c_int64, _f64p]
+        L.orc_mlp_forward.argtypes = [_f64p, _f32p, C.c_int64, C.c_int, _f64p]
+        L.orc_mlp_loss_grad.argtypes = [_f64p, _f32p, _f64p, C.c_int64, C.c_double, C.c_int,
+                                        C.POINTER(C.c_double), _f64p]
+        L.orc_adam.argtypes = [_f64p, _f64p, _f64p, _f64p, C.c_int64, C.c_double, C.c_double,
+                               C.c_double, C.c_double, C.c_int]
+        L.orc_lists_learned.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float,
+                                        vp, vp, vp, vp, C.c_int64, vp, vp, vp, vp,
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
         _lib = L
     return _lib
 
@@ -152,6 +165,62 @@ class Tree:
         lib().orc_counts(self._h, float(theta), out)
         return out
 
+    # ---- learned acceptance criterion (oracle_mac.cpp)
+    def mac_features(self, g, c):
+        g = np.ascontiguousarray(g, np.int32)
+        c = np.ascontiguousarray(c, np.int32)
+        out = np.zeros((g.shape[0], 12), np.float32)
+        lib().orc_mac_features(self._h, g, c, g.shape[0], out)
+        return out
+
+    def mac_band(self, theta_lo=0.3, theta_hi=1.0, groups=None):
+        """(group index, cell id) band candidates of the theta_lo walks."""
+        sel = None if groups is None else np.ascontiguousarray(groups, np.int32)
+        n = C.c_int64()
+        lib().orc_mac_band(self._h, theta_lo, theta_hi, _ptr(sel), 0 if sel is None else sel.size,
+                           None, None, 0, C.byref(n))
+        g = np.zeros(max(1, n.value), np.int32)
+        c = np.zeros(max(1, n.value), np.int32)
+        lib().orc_mac_band(self._h, theta_lo, theta_hi, _ptr(sel), 0 if sel is None else sel.size,
+                           _ptr(g), _ptr(c), n.value, C.byref(n))
+        return g[:n.value], c[:n.value]
+
+    def mac_labels(self, acc_direct, eps, g, c):
+        g = np.ascontiguousarray(g, np.int32)
+        c = np.ascontiguousarray(c, np.int32)
+        out = np.zeros(g.shape[0])
+        lib().orc_mac_labels(self._h, np.ascontiguousarray(acc_direct, np.float64), float(eps),
+                             g, c, g.shape[0], out)
+        return out
+
+    def lists_learned(self, theta, theta_lo, theta_hi, log10_tau, budget, params=None,
+                      replay=None):
+        """Lists under the learned criterion (network `params`, or a replay
+        (g, c, score) table sorted by (g, c)); returns lists + fell_back."""
+        P = None if params is None else np.ascontiguousarray(params, np.float64)
+        if replay is not None:
+            rg, rc, rs = (np.ascontiguousarray(replay[0], np.int32),
+                          np.ascontiguousarray(replay[1], np.int32),
+                          np.ascontiguousarray(replay[2], np.float32))
+            nr = rg.shape[0]
+        else:
+            rg = rc = rs = None
+            nr = 0
+        nc, nl = C.c_int64(), C.c_int64()
+        args = (self._h, float(theta), float(theta_lo), float(theta_hi), float(log10_tau),
+                float(budget), _ptr(P), _ptr(rg), _ptr(rc), _ptr(rs), nr)
+        rc_ = lib().orc_lists_learned(*args, None, None, None, None, C.byref(nc), C.byref(nl), None)
+        if rc_ != 0:
+            raise ValueError("replay table misses a band candidate")
+        c_off = np.zeros(self.n_groups + 1, np.int64)
+        l_off = np.zeros(self.n_groups + 1, np.int64)
+        c_ids = np.zeros(max(1, nc.value), np.int32)
+        l_ids = np.zeros(max(1, nl.value), np.int32)
+        fb = np.zeros(self.n_groups, np.int32)
+        lib().orc_lists_learned(*args, _ptr(c_off), _ptr(c_ids), _ptr(l_off), _ptr(l_ids),
+                                C.byref(nc), C.byref(nl), _ptr(fb))
+        return (c_off, c_ids[:nc.value], l_off, l_ids[:nl.value]), fb
+
     def forces(self, theta, eps, groups=None):
         """FP64 same-tree forces; (acc [n,3], pot [n]) by input index.  With
         `groups`, only those groups' particles are filled (others are NaN)."""
@@ -162,6 +231,34 @@ class Tree:
                               0 if sel is None else sel.shape[0], acc, _ptr(pot))
         assert rc == 0
         return acc, pot
+
+
+def mlp_params() -> int:
+    return int(lib().orc_mlp_params())
+
+
+def mlp_forward(params, x, round_bf16=True):
+    x = np.ascontiguousarray(x, np.float32).reshape(-1, 12)
+    y = np.zeros(x.shape[0])
+    lib().orc_mlp_forward(np.ascontiguousarray(params, np.float64), x, x.shape[0],
+                          int(bool(round_bf16)), y)
+    return y
+
+
+def mlp_loss_grad(params, x, target, tau=0.9, round_bf16=True):
+    x = np.ascontiguousarray(x, np.float32).reshape(-1, 12)
+    g = np.zeros(mlp_params())
+    loss = C.c_double()
+    lib().orc_mlp_loss_grad(np.ascontiguousarray(params, np.float64), x,
+                            np.ascontiguousarray(target, np.float64), x.shape[0], float(tau),
+                            int(bool(round_bf16)), C.byref(loss), g)
+    return loss.value, g
+
+
+def adam_step(params, m, v, grad, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays (step counted from 1)."""
+    lib().orc_adam(params, m, v, np.ascontiguousarray(grad, np.float64), params.shape[0],
+                   lr, b1, b2, eps, int(step))
 
 
 def diagnostics(mass, acc, pot):

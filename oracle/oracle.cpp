@@ -37,31 +37,9 @@
 
 #include <omp.h>
 
-namespace {
+#include "oracle_tree.h"
 
-constexpr int kMaxDepth = 21;
-
-struct Cell {
-  int64_t first = 0, n = 0;  // contiguous range of the oracle's particle order
-  int depth = 0, parent = -1;
-  int first_child = -1, n_child = 0;
-  double corner[3] = {0, 0, 0}, side = 0;  // the octree cube of this cell
-  double mn[3], mx[3];                     // tight bounding box
-  double cb[3], l;                         // boundary cube: centre and side
-  double M, com[3], Q[6];                  // Q: xx, yy, zz, xy, xz, yz
-  float geo[4];                            // FP32 boundary: the opening-test input
-};
-
-struct Tree {
-  int64_t n = 0;
-  int n_leaf = 0, n_group = 0;
-  std::vector<double> x[3], m;
-  std::vector<int32_t> order;  // oracle order position -> input index
-  std::vector<Cell> cells;     // breadth-first order
-  std::vector<int32_t> groups; // group cell ids, ascending first particle
-  double L[3] = {0, 0, 0}, S = 1;
-  int max_depth = 0;
-};
+namespace orc {
 
 // Octant of point p in the cube (corner, side): each coordinate goes to the
 // upper half iff it is >= the cube's midplane.
@@ -405,7 +383,9 @@ void eval_group(const Tree& t, int32_t gcell, const std::vector<int32_t>& C,
   }
 }
 
-}  // namespace
+}  // namespace orc
+
+using namespace orc;
 
 extern "C" {
 
