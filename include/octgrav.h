@@ -174,6 +174,34 @@ int octgrav_last_counts(octgrav_tree* t, int64_t out[4]);
  * out[5] total. */
 int octgrav_last_timings(octgrav_tree* t, double out[6]);
 
+/*
+ * Direct summation on the GPU (FP32 with compensated accumulation), the
+ * reference the paper measures its errors against (Sec. 3.1) and the
+ * normalization of the learned criterion's labels.
+ *   targets  device int32 caller indices, or NULL for all n particles
+ *   nt       number of targets (ignored when targets is NULL)
+ *   acc      device, nt x 3 FP32 in target order; pot device nt FP32 or NULL
+ * Softened like the tree forces (eps > 0), self excluded.  Synchronous.
+ * Target indices outside [0, n) give OCTGRAV_EINVAL before any launch.
+ */
+int octgrav_direct(octgrav_tree* t, float eps, const int32_t* targets, int64_t nt, float* acc,
+                   float* pot);
+
+/*
+ * Training data of the learned acceptance criterion.  Walks every group at
+ * theta_lo and keeps the band candidates (cells the theta_lo test opens and
+ * the theta_hi test does not); for the groups g = 0, stride, 2*stride, ...
+ * (while the pairs fit in cap) writes for each pair its 12 FP32 features
+ * (device feat, cap x 12) and its label e = max over the group's particles i
+ * of |a_pc(i; c) - sum_{j in c} a_pp(i, j)| / |a_i| (device label, cap),
+ * with |a_i| from acc_direct (device, n x 3 caller order, e.g. from
+ * octgrav_direct), and optionally the pair's group index and cell id (device
+ * int32 arrays, cap, or NULL).  *n_out = pairs written.  Synchronous.
+ */
+int octgrav_mac_collect(octgrav_tree* t, float theta_lo, float theta_hi, float eps,
+                        const float* acc_direct, int32_t stride, float* feat, float* label,
+                        int32_t* group_out, int32_t* cell_out, int64_t cap, int64_t* n_out);
+
 #ifdef __cplusplus
 }
 #endif

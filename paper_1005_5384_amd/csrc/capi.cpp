@@ -135,6 +135,16 @@ struct octgrav_tree {
       std::memcpy(&wrec[8 * c], &geo_dev[4 * c], 16);
       std::memcpy(&wrec[8 * c + 4], &h.topo[4 * c], 16);
     }
+    // Feature inputs of the learned criterion: FP32 tight-box extents and
+    // the level of each cell; and the inverse permutation for direct sums.
+    std::vector<float> ext((size_t)nc * 4);
+    for (int64_t c = 0; c < nc; ++c) {
+      for (int k = 0; k < 3; ++k) ext[4 * c + k] = (float)(h.box[6 * c + 3 + k] - h.box[6 * c + k]);
+      ext[4 * c + 3] = (float)h.depth[c];
+    }
+    std::vector<int32_t> iperm(n);
+    for (int64_t i = 0; i < n; ++i) iperm[h.perm[i]] = (int32_t)i;
+    if ((rc = upload(ext, &dt.ext)) || (rc = upload(iperm, &dt.iperm))) return rc;
     if ((rc = upload(h.part, &dt.part)) || (rc = upload(h.perm, &dt.perm)) ||
         (rc = upload(h.topo, &dt.topo)) || (rc = upload(geo_dev, &dt.geo)) ||
         (rc = upload(wrec, &dt.wrec)) ||
@@ -536,6 +546,91 @@ int octgrav_last_counts(octgrav_tree* t, int64_t out[4]) {
   if (int rc = t->read_tot(tot)) return rc;
   for (int k = 0; k < 4; ++k) out[k] = tot[k];
   return OCTGRAV_OK;
+}
+
+int octgrav_direct(octgrav_tree* t, float eps, const int32_t* targets, int64_t nt, float* acc,
+                   float* pot) {
+  g_err.clear();
+  if (!t) return fail(OCTGRAV_EINVAL, "NULL handle");
+  if (!t->dev) return fail(OCTGRAV_EINVAL, "tree was built host-only");
+  if (!(eps > 0.0f) || !std::isfinite(eps)) return fail(OCTGRAV_EINVAL, "eps must be finite and > 0");
+  if (!acc) return fail(OCTGRAV_EINVAL, "acc must be non-NULL");
+  if (!targets) nt = t->h.n;
+  if (nt < 0) return fail(OCTGRAV_EINVAL, "nt must be >= 0");
+  if (targets && nt > 0) {  // indices are checked on the host before any kernel reads them
+    std::vector<int32_t> tg(nt);
+    if (hipMemcpy(tg.data(), targets, nt * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(OCTGRAV_EINVAL, "targets is not readable device memory");
+    for (int32_t v : tg)
+      if (v < 0 || v >= t->h.n) return fail(OCTGRAV_EINVAL, "target index out of range");
+  }
+  if (launch_direct(t->dt, targets, nt, eps, acc, pot, t->stream))
+    return fail(OCTGRAV_EHIP, "direct-sum launch failed");
+  if (hipStreamSynchronize(t->stream) != hipSuccess)
+    return fail(OCTGRAV_EHIP, std::string("device error: ") + hipGetErrorString(hipGetLastError()));
+  return OCTGRAV_OK;
+}
+
+int octgrav_mac_collect(octgrav_tree* t, float theta_lo, float theta_hi, float eps,
+                        const float* acc_direct, int32_t stride, float* feat, float* label,
+                        int32_t* group_out, int32_t* cell_out, int64_t cap, int64_t* n_out) {
+  g_err.clear();
+  if (int rc = check_theta(t, theta_lo)) return rc;
+  if (!(theta_hi > theta_lo && theta_hi <= 1.0f)) return fail(OCTGRAV_EINVAL, "need theta_lo < theta_hi <= 1");
+  if (!(eps > 0.0f)) return fail(OCTGRAV_EINVAL, "eps must be > 0");
+  if (!acc_direct || !feat || !label || !n_out || stride < 1 || cap < 0)
+    return fail(OCTGRAV_EINVAL, "bad collect arguments");
+  try {
+    // Band lists of every group (count walk, offsets, write walk in band mode).
+    WalkBufs saved = t->wb;
+    t->wb.band = 1;
+    t->wb.band_hi2 = theta_hi * theta_hi;
+    int64_t tot[8];
+    int rc = 0;
+    if (launch_walk(t->dt, t->wb, theta_lo, 0, t->stream) || launch_scan(t->dt, t->wb, t->stream))
+      rc = fail(OCTGRAV_EHIP, "band walk launch failed");
+    if (!rc) rc = t->read_tot(tot);
+    if (!rc && tot[5]) rc = fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+    if (!rc) rc = t->reserve_lists(tot[0], 1);
+    if (!rc) {
+      WalkBufs b = t->wb;  // reserve_lists may have moved the buffers
+      b.band = 1;
+      b.band_hi2 = theta_hi * theta_hi;
+      if (launch_walk(t->dt, b, theta_lo, 1, t->stream)) rc = fail(OCTGRAV_EHIP, "band walk launch failed");
+    }
+    const int64_t ng = t->h.n_groups();
+    std::vector<int64_t> c_off(ng + 1);
+    if (!rc && hipMemcpy(c_off.data(), t->wb.c_off, (ng + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      rc = fail(OCTGRAV_EHIP, "offsets copy-back failed");
+    t->wb.band = saved.band;
+    t->wb.band_hi2 = saved.band_hi2;
+    if (rc) return rc;
+    // Sampled groups while their pairs fit.
+    std::vector<int32_t> gs;
+    std::vector<int64_t> off{0};
+    for (int64_t g = 0; g < ng; g += stride) {
+      const int64_t k = c_off[g + 1] - c_off[g];
+      if (off.back() + k > cap) break;
+      gs.push_back((int32_t)g);
+      off.push_back(off.back() + k);
+    }
+    const int64_t np = off.back();
+    *n_out = np;
+    if (np == 0) return OCTGRAV_OK;
+    void *dg = nullptr, *doff = nullptr;
+    if ((rc = t->dalloc(&dg, gs.size() * 4)) || (rc = t->dalloc(&doff, off.size() * 8))) return rc;
+    hipMemcpy(dg, gs.data(), gs.size() * 4, hipMemcpyHostToDevice);
+    hipMemcpy(doff, off.data(), off.size() * 8, hipMemcpyHostToDevice);
+    rc = launch_mac_labels(t->dt, t->wb, (const int32_t*)dg, (int64_t)gs.size(), (const int64_t*)doff,
+                           acc_direct, eps, feat, label, group_out, cell_out, np, t->stream);
+    if (!rc && hipStreamSynchronize(t->stream) != hipSuccess) rc = -1;
+    t->dfree(dg);
+    t->dfree(doff);
+    if (rc) return fail(OCTGRAV_EHIP, "label kernel failed");
+    return OCTGRAV_OK;
+  } catch (const std::exception& e) {
+    return fail(OCTGRAV_EHIP, e.what());
+  }
 }
 
 int octgrav_last_timings(octgrav_tree* t, double out[6]) {

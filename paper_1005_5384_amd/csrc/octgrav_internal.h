@@ -44,6 +44,8 @@ struct DevTree {
   const int32_t* topo;   // int4 [nc]
   const float* geo;      // float4 [nc]  boundary; the side's sign bit marks leaves
   const float* wrec;     // float4 x2 [nc] walk record: boundary (as geo) | topo
+  const float* ext;      // float4 [nc] FP32 tight-box extents xyz, depth
+  const int32_t* iperm;  // [n] caller index -> sorted position
   const float* mp;       // float4 x3 [nc]
   const int32_t* ginfo;  // int4 [ng]
   const float* gbox;     // float4 x2 [ng]
@@ -70,6 +72,10 @@ struct WalkBufs {
   // Slotted lists (walk mode 2, > 0): group g's lists start at g * slot_c /
   // g * slot_l and their lengths are cnt[g].x / .y; 0 = CSR offsets.
   int64_t slot_c, slot_l;
+  // Band collection (band != 0): the "cell list" records the candidates the
+  // walk's test opens and the test at band_hi2 (squared angle) does not.
+  int32_t band;
+  float band_hi2;
 };
 
 // Kernel launchers (device sources).  mode 0 = count, 1 = write at the
@@ -86,6 +92,15 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
                      bool do_eval, float* acc, float* pot, void* stream);
 int launch_walk_eval_block(const DevTree& T, const WalkBufs& B, float theta, float eps, bool plain,
                            bool do_eval, float* acc, float* pot, void* stream);
+// FP32 compensated direct sum for targets (caller indices, device array, or
+// NULL = all); outputs in target order.
+int launch_direct(const DevTree& T, const int32_t* targets, int64_t nt, float eps, float* acc,
+                  float* pot, void* stream);
+// Features (12, FP32) and labels of the band pairs of the listed groups
+// (pair p of listed group s sits at out_off[s] + k); also each pair's ids.
+int launch_mac_labels(const DevTree& T, const WalkBufs& B, const int32_t* groups, int64_t ngs,
+                      const int64_t* out_off, const float* acc_direct, float eps, float* feat,
+                      float* label, int32_t* gout, int32_t* cout, int64_t npairs, void* stream);
 int launch_diag(const DevTree& T, const float* acc, const float* pot, double* part_sums,
                 double* out4, void* stream);
 int64_t scan_scratch_entries(int64_t ng);

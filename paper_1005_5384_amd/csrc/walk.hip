@@ -53,9 +53,11 @@ __device__ void walk_group(const DevTree& T, const WalkBufs& B, int64_t g, float
   }
   const int4 root = reinterpret_cast<const int4*>(rec)[1];
   if (root.y == 0) {  // the root is a leaf: every group sees all particles directly
-    nL = 1;
-    nsrc = root.w;
-    if (MODE != 0 && lane == 0) B.l_ids[lb] = 0;
+    if (!B.band) {
+      nL = 1;
+      nsrc = root.w;
+      if (MODE != 0 && lane == 0) B.l_ids[lb] = 0;
+    }
   } else {
     uint32_t head = 0, tail = (uint32_t)root.y;
     if (lane < root.y) q[lane] = root.x + lane;
@@ -69,8 +71,10 @@ __device__ void walk_group(const DevTree& T, const WalkBufs& B, int64_t g, float
       const float4 ge = rec[2 * (int64_t)c];
       const int4 tp = reinterpret_cast<const int4*>(rec)[2 * (int64_t)c + 1];
       const bool op = valid && open_cell(gmin, gmax, ge, th2);
-      const bool toC = valid && !op;
-      const bool toL = op && tp.y == 0;
+      // Band collection records opened candidates that the wider test at
+      // band_hi2 would not open; otherwise the cell / leaf lists of Sec. 2.2.
+      const bool toC = B.band ? (op && !open_cell(gmin, gmax, ge, B.band_hi2)) : (valid && !op);
+      const bool toL = !B.band && op && tp.y == 0;
       const bool push = op && tp.y != 0;
       const uint64_t mC = __ballot(toC), mL = __ballot(toL);
       if (MODE == 1) {

@@ -46,7 +46,7 @@ class TreeView(C.Structure):
 EXPORTED = ["octgrav_build_tree", "octgrav_build_tree_ex", "octgrav_forces", "octgrav_forces_ex",
             "octgrav_free", "octgrav_last_error", "octgrav_set_stream", "octgrav_tree_stats",
             "octgrav_export_tree", "octgrav_lists", "octgrav_lists_ex", "octgrav_diagnostics",
-            "octgrav_last_counts",
+            "octgrav_last_counts", "octgrav_direct", "octgrav_mac_collect",
             "octgrav_last_timings"]
 
 
@@ -81,6 +81,9 @@ def lib():
         L.octgrav_diagnostics.argtypes = [vp, vp, vp]
         L.octgrav_last_counts.argtypes = [vp, vp]
         L.octgrav_last_timings.argtypes = [vp, vp]
+        L.octgrav_direct.argtypes = [vp, f32, vp, i64, vp, vp]
+        L.octgrav_mac_collect.argtypes = [vp, f32, f32, f32, vp, i32, vp, vp, vp, vp, i64,
+                                          C.POINTER(i64)]
         _lib = L
     return _lib
 
@@ -164,6 +167,42 @@ class Tree:
         _check(lib().octgrav_lists_ex(self._h, float(theta), fl, _ptr(c_off), _ptr(c_ids),
                                       _ptr(l_off), _ptr(l_ids), C.byref(nc), C.byref(nl)))
         return c_off, c_ids[:nc.value], l_off, l_ids[:nl.value]
+
+    def direct(self, eps, targets=None):
+        """FP32 compensated GPU direct sum: (acc [nt,3], pot [nt]) torch tensors
+        for the caller indices `targets` (a sequence or tensor; None = all)."""
+        import torch
+        self._bind_stream()
+        tg = None
+        if targets is not None:
+            tg = torch.as_tensor(targets, dtype=torch.int32, device="cuda").contiguous()
+        nt = self.n if tg is None else tg.numel()
+        acc = torch.empty((nt, 3), dtype=torch.float32, device="cuda")
+        pot = torch.empty(nt, dtype=torch.float32, device="cuda")
+        if nt == 0:  # an empty tensor has no address; NULL targets would mean "all"
+            return acc, pot
+        _check(lib().octgrav_direct(self._h, float(eps),
+                                    None if tg is None else C.c_void_p(tg.data_ptr()), nt,
+                                    C.c_void_p(acc.data_ptr()), C.c_void_p(pot.data_ptr())))
+        return acc, pot
+
+    def mac_collect(self, eps, acc_direct, theta_lo=0.3, theta_hi=1.0, stride=1, cap=1 << 22):
+        """Band pairs' features [k,12], labels [k], group ids, cell ids (torch)."""
+        import torch
+        self._bind_stream()
+        feat = torch.empty((cap, 12), dtype=torch.float32, device="cuda")
+        lab = torch.empty(cap, dtype=torch.float32, device="cuda")
+        gid = torch.empty(cap, dtype=torch.int32, device="cuda")
+        cid = torch.empty(cap, dtype=torch.int32, device="cuda")
+        n = C.c_int64()
+        acc_direct = acc_direct.contiguous()
+        _check(lib().octgrav_mac_collect(self._h, float(theta_lo), float(theta_hi), float(eps),
+                                         C.c_void_p(acc_direct.data_ptr()), int(stride),
+                                         C.c_void_p(feat.data_ptr()), C.c_void_p(lab.data_ptr()),
+                                         C.c_void_p(gid.data_ptr()), C.c_void_p(cid.data_ptr()),
+                                         cap, C.byref(n)))
+        k = n.value
+        return feat[:k], lab[:k], gid[:k], cid[:k]
 
     def export(self):
         s = self.stats
