@@ -202,6 +202,69 @@ int octgrav_mac_collect(octgrav_tree* t, float theta_lo, float theta_hi, float e
                         const float* acc_direct, int32_t stride, float* feat, float* label,
                         int32_t* group_out, int32_t* cell_out, int64_t cap, int64_t* n_out);
 
+/*
+ * ---- Learned acceptance criterion (an extension of the opening test of
+ * Sec. 2.2; the paper itself uses the opening angle only).
+ *
+ * The network maps 12 features of a (group, cell) candidate to a predicted
+ * log10 of the cell's relative force error on the group: 12 -> 64 -> 64 -> 1
+ * with ReLU, 5057 FP32 parameters laid out as W1 [64 x 12] row-major, b1
+ * [64], W2 [64 x 64] row-major, b2 [64], w3 [64], b3.  Inference rounds the
+ * inputs, weights and hidden activations to BF16 (nearest even) and
+ * accumulates in FP32 on the matrix cores.
+ */
+typedef struct octgrav_mlp octgrav_mlp;
+
+/* A network with the given parameters (host, 5057 FP32; NULL = zeros) and
+ * zero Adam moments.  NULL on failure (octgrav_last_error). */
+octgrav_mlp* octgrav_mlp_create(const float* params);
+void octgrav_mlp_free(octgrav_mlp* m); /* NULL-safe */
+int octgrav_mlp_set_stream(octgrav_mlp* m, void* hip_stream);
+/* Replaces the parameters (host, 5057 FP32, finite) and zeroes the moments. */
+int octgrav_mlp_set_params(octgrav_mlp* m, const float* params);
+int octgrav_mlp_get_params(const octgrav_mlp* m, float* params);
+/* y[b] (device FP32) for inputs x (device, b x 12 FP32).  Synchronous. */
+int octgrav_mlp_forward(octgrav_mlp* m, const float* x, int64_t b, float* y);
+/*
+ * Mean pinball loss at quantile tau in (0, 1) of targets (device, b FP32) and
+ * its gradient, kept in the handle for octgrav_mlp_adam and optionally copied
+ * to grad (host, 5057 FP32, may be NULL).  *loss is FP64.  Weight gradients
+ * use the BF16-rounded activation gradients and activations, bias gradients
+ * the unrounded ones.  Synchronous.
+ */
+int octgrav_mlp_loss_grad(octgrav_mlp* m, const float* x, const float* target, int64_t b,
+                          float tau, double* loss, float* grad);
+/* One Adam step (Kingma & Ba, bias-corrected; step counts from 1) with the
+ * last gradient, then the BF16 inference image is rebuilt.  Synchronous. */
+int octgrav_mlp_adam(octgrav_mlp* m, float lr, float beta1, float beta2, float eps, int32_t step);
+
+/*
+ * Sets the tree's acceptance criterion.  m == NULL: the opening angle (the
+ * default).  Otherwise a copy of m's current network is taken and, in later
+ * octgrav_forces / octgrav_lists calls, a candidate the theta_lo test accepts
+ * is accepted, one the theta_hi test opens is opened, and in between it is
+ * accepted iff the network's output <= log10(tau_pair) (tau_pair = 0: never).
+ * A group whose network-accepted candidates have sqrt(sum 10^(2 y)) > budget
+ * is walked with the call's theta instead (budget < 0: every group).
+ * Needs 0 < theta_lo < theta_hi <= 1.  These calls then use the fused wave
+ * path (OCTGRAV_TWO_PASS / OCTGRAV_FUSED_BLOCK give OCTGRAV_EINVAL).
+ */
+int octgrav_set_mac(octgrav_tree* t, const octgrav_mlp* m, float theta_lo, float theta_hi,
+                    float tau_pair, float budget);
+/* After a forces / lists call with the learned criterion: out[0] = band
+ * candidates the network scored, out[1] = groups that fell back to theta. */
+int octgrav_mac_stats(octgrav_tree* t, int64_t out[2]);
+/*
+ * Decision trace of the learned walks at this theta (test export): off
+ * (host, n_groups + 1) receives group g's range of trace entries, fell_back
+ * (host, n_groups) 1 for the groups walked with theta; with cells and scores
+ * (host, cap entries) non-NULL, the band candidates' cell ids and network
+ * outputs in walk order (the fell-back groups' entries are those of their
+ * learned attempt).  *n_out = entries.  Two-call pattern as octgrav_lists.
+ */
+int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells, float* scores,
+                      int64_t cap, int64_t* n_out, int32_t* fell_back);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,6 +44,8 @@ def lib():
             f.argtypes = [vp, C.c_float, vp, vp, vp, vp, vp, vp]
         L.orc_forces.argtypes = [vp, C.c_float, C.c_float, vp, C.c_int64, _f64p, vp]
         L.orc_counts.argtypes = [vp, C.c_float, _i64p]
+        L.orc_forces_lists.argtypes = [vp, C.c_float, _i64p, _i32p, _i64p, _i32p, vp, C.c_int64,
+                                       _f64p, vp]
         L.orc_diagnostics.argtypes = [_f32p, _f64p, vp, C.c_int64, _f64p]
         L.orc_num_threads.restype = C.c_int
         L.orc_mlp_params.restype = C.c_int
@@ -231,6 +233,28 @@ class Tree:
                               0 if sel is None else sel.shape[0], acc, _ptr(pot))
         assert rc == 0
         return acc, pot
+
+
+def _forces_lists(self, lists, eps, groups=None):
+    """FP64 forces from given CSR lists (c_off, c_ids, l_off, l_ids)."""
+    c_off, c_ids, l_off, l_ids = (np.ascontiguousarray(lists[0], np.int64),
+                                  np.ascontiguousarray(lists[1], np.int32),
+                                  np.ascontiguousarray(lists[2], np.int64),
+                                  np.ascontiguousarray(lists[3], np.int32))
+    if c_ids.size == 0:
+        c_ids = np.zeros(1, np.int32)
+    if l_ids.size == 0:
+        l_ids = np.zeros(1, np.int32)
+    acc = np.full((self.n, 3), np.nan)
+    pot = np.full(self.n, np.nan)
+    sel = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
+    rc = lib().orc_forces_lists(self._h, float(eps), c_off, c_ids, l_off, l_ids, _ptr(sel),
+                                0 if sel is None else sel.shape[0], acc, _ptr(pot))
+    assert rc == 0
+    return acc, pot
+
+
+Tree.forces_lists = _forces_lists
 
 
 def mlp_params() -> int:

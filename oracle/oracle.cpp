@@ -573,6 +573,26 @@ int orc_forces(const void* h, float theta, float eps, const int32_t* sel, int64_
   return 0;
 }
 
+// FP64 forces of the selected groups (all: sel == NULL) from given CSR lists
+// (cell ids; e.g. lists of another acceptance criterion), as orc_forces
+// evaluates its own walk's lists.
+int orc_forces_lists(const void* h, float eps, const int64_t* c_off, const int32_t* c_ids,
+                     const int64_t* l_off, const int32_t* l_ids, const int32_t* sel, int64_t n_sel,
+                     double* acc, double* pot) {
+  const Tree& t = *(const Tree*)h;
+  if (!acc) return -1;
+  int64_t ng = sel ? n_sel : (int64_t)t.groups.size();
+  double eps2 = (double)eps * (double)eps;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t u = 0; u < ng; ++u) {
+    const int64_t g = sel ? sel[u] : u;
+    std::vector<int32_t> C(c_ids + c_off[g], c_ids + c_off[g + 1]);
+    std::vector<int32_t> Lv(l_ids + l_off[g], l_ids + l_off[g + 1]);
+    eval_group(t, t.groups[g], C, Lv, eps2, acc, pot);
+  }
+  return 0;
+}
+
 // Interaction counts of the selected groups: per group |C_g|, |L_g| and the
 // number of source particles in L_g.
 int orc_counts(const void* h, float theta, int64_t* out3) {

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libocgrav.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["walk.hip", "eval.hip", "walk_eval.hip", "walk_eval_block.hip", "mac.hip"]
+HIP_SOURCES = ["walk.hip", "eval.hip", "walk_eval.hip", "walk_eval_block.hip", "mac.hip", "mlp.hip"]
 CPP_SOURCES = ["tree_build.cpp", "capi.cpp"]
 
 HIPCC_FLAGS = [
@@ -53,7 +53,7 @@ def build(verbose: bool = False, extra_hip_flags=()) -> str:
         list(ex.map(lambda j: _run(j[0], verbose), jobs))
     tmp = LIB + ".tmp"
     _run([f"{ROCM}/bin/hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
-          *[o for _, o in jobs], "-lgomp", f"-Wl,-rpath,{ROCM}/lib"], verbose)
+          *[o for _, o in jobs], "-lgomp", "-Wl,--no-undefined", f"-Wl,-rpath,{ROCM}/lib"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -58,6 +58,42 @@ int lds_queue_entries() {
 
 }  // namespace
 
+// Network of the learned criterion: FP32 master parameters, Adam moments,
+// the last gradient, the packed BF16 inference image and training scratch.
+struct octgrav_mlp {
+  hipStream_t stream = nullptr;
+  void *P = nullptr, *mom1 = nullptr, *mom2 = nullptr, *grad = nullptr, *pk = nullptr,
+       *d_loss = nullptr, *scratch = nullptr;
+  int64_t scratch_b = 0;
+  std::vector<void*> allocs;
+
+  ~octgrav_mlp() {
+    for (void* p : allocs) hipFree(p);
+  }
+  int alloc(void** p, size_t bytes) {
+    if (alloc_fault() || hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return fail(OCTGRAV_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    allocs.push_back(*p);
+    return OCTGRAV_OK;
+  }
+  // Training scratch for batches of up to b samples: 3 b + 4 x 64 b floats.
+  int reserve(int64_t b) {
+    if (b <= scratch_b) return OCTGRAV_OK;
+    if (scratch) {
+      hipFree(scratch);
+      allocs.erase(std::find(allocs.begin(), allocs.end(), scratch));
+      scratch = nullptr;
+      scratch_b = 0;
+    }
+    if (int rc = alloc(&scratch, (size_t)(3 + 4 * 64) * b * 4)) return rc;
+    scratch_b = b;
+    return OCTGRAV_OK;
+  }
+};
+
 struct octgrav_tree {
   HostTree h;
   bool dev = false;
@@ -78,6 +114,9 @@ struct octgrav_tree {
   hipEvent_t bev[kBatches + 2] = {};
   std::vector<int64_t> gwork;  // [ng+1] first work item of each group
   int64_t slot_c = 0, slot_l = 0;  // per-group list slots of the pipelined path (0 = unsized)
+  // Learned acceptance criterion: a private copy of the network's packed image.
+  void* d_mlp = nullptr;
+  bool learned = false;
 
   ~octgrav_tree() {
     for (void* p : allocs) hipFree(p);
@@ -407,7 +446,9 @@ int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float
     t->counts_valid = false;
     t->have_diag = false;
     int64_t tot[8];
-    const Path path = choose_path(flags, theta);
+    if (t->learned && (flags & (OCTGRAV_TWO_PASS | OCTGRAV_FUSED_BLOCK)))
+      return fail(OCTGRAV_EINVAL, "the learned criterion runs on the fused wave path only");
+    const Path path = t->learned ? Path::FusedWave : choose_path(flags, theta);
     for (int attempt = 0; attempt < 2; ++attempt) {
       if (timed) {
         for (int k = 0; k < 4; ++k) hipEventRecord(t->ev[k], t->stream);
@@ -486,15 +527,21 @@ int octgrav_lists_ex(octgrav_tree* t, float theta, uint32_t flags, int64_t* c_of
   try {
     t->counts_valid = false;
     int64_t tot[8];
+    if (t->learned && (flags & (OCTGRAV_TWO_PASS | OCTGRAV_FUSED_BLOCK)))
+      return fail(OCTGRAV_EINVAL, "the learned criterion runs on the fused wave path only");
     // Count walk and offsets give the sizes; the buffers are made to fit.
-    if (launch_walk(t->dt, t->wb, theta, 0, t->stream)) return fail(OCTGRAV_EHIP, "count walk launch failed");
+    // (The learned criterion counts with the fused walk itself.)
+    t->wb.export_lists = 0;
+    if (t->learned ? launch_fused(t, Path::FusedWave, theta, 1.0f, false, false, nullptr, nullptr) != 0
+                   : launch_walk(t->dt, t->wb, theta, 0, t->stream) != 0)
+      return fail(OCTGRAV_EHIP, "count walk launch failed");
     if (launch_scan(t->dt, t->wb, t->stream)) return fail(OCTGRAV_EHIP, "offsets launch failed");
     if (int rc = t->read_tot(tot)) return rc;
     if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
     if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
     *n_c = tot[0];
     *n_l = tot[1];
-    const Path path = choose_path(flags, theta);
+    const Path path = t->learned ? Path::FusedWave : choose_path(flags, theta);
     if (path == Path::TwoPass) {
       if (launch_walk(t->dt, t->wb, theta, 1, t->stream)) return fail(OCTGRAV_EHIP, "write walk launch failed");
     } else {
@@ -631,6 +678,214 @@ int octgrav_mac_collect(octgrav_tree* t, float theta_lo, float theta_hi, float e
   } catch (const std::exception& e) {
     return fail(OCTGRAV_EHIP, e.what());
   }
+}
+
+int octgrav_set_mac(octgrav_tree* t, const octgrav_mlp* m, float theta_lo, float theta_hi,
+                    float tau_pair, float budget) {
+  g_err.clear();
+  if (!t) return fail(OCTGRAV_EINVAL, "NULL handle");
+  if (!t->dev) return fail(OCTGRAV_EINVAL, "tree was built host-only");
+  if (!m) {
+    t->learned = false;
+    t->wb.mlp = nullptr;
+    return OCTGRAV_OK;
+  }
+  if (!(theta_lo > 0.0f && theta_lo < theta_hi && theta_hi <= 1.0f))
+    return fail(OCTGRAV_EINVAL, "need 0 < theta_lo < theta_hi <= 1");
+  if (!(tau_pair >= 0.0f) || std::isnan(budget)) return fail(OCTGRAV_EINVAL, "need tau_pair >= 0 and a budget");
+  if (!t->d_mlp)
+    if (int rc = t->dalloc(&t->d_mlp, kPkBytes)) return rc;
+  if (hipMemcpy(t->d_mlp, m->pk, kPkBytes, hipMemcpyDeviceToDevice) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "network copy failed");
+  t->learned = true;
+  t->wb.mlp = (const uint8_t*)t->d_mlp;
+  t->wb.mac_lo2 = theta_lo * theta_lo;
+  t->wb.mac_hi2 = theta_hi * theta_hi;
+  t->wb.mac_ltau = tau_pair > 0.0f ? std::log10(tau_pair) : -INFINITY;
+  t->wb.mac_budget = (double)budget;
+  return OCTGRAV_OK;
+}
+
+// Per-group learned-walk records of the last fused call: band candidates
+// visited and fall-back flags (host copies of cnt[].w).
+static int read_band_counts(octgrav_tree* t, std::vector<int32_t>& w) {
+  const int64_t ng = t->h.n_groups();
+  std::vector<int32_t> cnt(4 * ng);
+  if (hipMemcpy(cnt.data(), t->wb.cnt, ng * 16, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "count copy-back failed");
+  w.resize(ng);
+  for (int64_t g = 0; g < ng; ++g) w[g] = cnt[4 * g + 3];
+  return OCTGRAV_OK;
+}
+
+int octgrav_mac_stats(octgrav_tree* t, int64_t out[2]) {
+  g_err.clear();
+  if (!t || !out) return fail(OCTGRAV_EINVAL, "NULL argument");
+  if (!t->learned || !t->counts_valid)
+    return fail(OCTGRAV_EINVAL, "no completed call with the learned criterion");
+  std::vector<int32_t> w;
+  if (int rc = read_band_counts(t, w)) return rc;
+  out[0] = out[1] = 0;
+  for (int32_t v : w) {
+    out[0] += v >> 1;
+    out[1] += v & 1;
+  }
+  return OCTGRAV_OK;
+}
+
+int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells, float* scores,
+                      int64_t cap, int64_t* n_out, int32_t* fell_back) {
+  g_err.clear();
+  if (int rc = check_theta(t, theta)) return rc;
+  if (!t->learned) return fail(OCTGRAV_EINVAL, "the learned criterion is not set");
+  if (!off || !n_out || !fell_back) return fail(OCTGRAV_EINVAL, "off, n_out and fell_back must be non-NULL");
+  try {
+    t->counts_valid = false;
+    const int64_t ng = t->h.n_groups();
+    t->wb.export_lists = 0;
+    if (launch_fused(t, Path::FusedWave, theta, 1.0f, false, false, nullptr, nullptr))
+      return fail(OCTGRAV_EHIP, "walk launch failed");
+    int64_t tot[8];
+    if (int rc = t->read_tot(tot)) return rc;
+    if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+    std::vector<int32_t> w;
+    if (int rc = read_band_counts(t, w)) return rc;
+    off[0] = 0;
+    for (int64_t g = 0; g < ng; ++g) {
+      off[g + 1] = off[g] + (w[g] >> 1);
+      fell_back[g] = w[g] & 1;
+    }
+    *n_out = off[ng];
+    t->counts_valid = true;
+    if (!cells || !scores) return OCTGRAV_OK;
+    if (cap < off[ng]) return fail(OCTGRAV_EINVAL, "trace arrays too small");
+    const int64_t nt = off[ng];
+    void *d_off = nullptr, *d_c = nullptr, *d_s = nullptr;
+    int rc = OCTGRAV_OK;
+    if ((rc = t->dalloc(&d_off, (ng + 1) * 8)) || (rc = t->dalloc(&d_c, nt * 4)) ||
+        (rc = t->dalloc(&d_s, nt * 4))) {
+      t->dfree(d_off);
+      t->dfree(d_c);
+      return rc;
+    }
+    hipMemcpy(d_off, off, (ng + 1) * 8, hipMemcpyHostToDevice);
+    WalkBufs saved = t->wb;
+    t->wb.tr_off = (const int64_t*)d_off;
+    t->wb.tr_c = (int32_t*)d_c;
+    t->wb.tr_s = (float*)d_s;
+    if (launch_fused(t, Path::FusedWave, theta, 1.0f, false, false, nullptr, nullptr))
+      rc = fail(OCTGRAV_EHIP, "walk launch failed");
+    t->wb.tr_off = saved.tr_off;
+    t->wb.tr_c = saved.tr_c;
+    t->wb.tr_s = saved.tr_s;
+    if (!rc && (hipMemcpy(cells, d_c, nt * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(scores, d_s, nt * 4, hipMemcpyDeviceToHost) != hipSuccess))
+      rc = fail(OCTGRAV_EHIP, "trace copy-back failed");
+    t->dfree(d_off);
+    t->dfree(d_c);
+    t->dfree(d_s);
+    return rc;
+  } catch (const std::exception& e) {
+    return fail(OCTGRAV_EHIP, e.what());
+  }
+}
+
+// ------------------------------------------------------------------ network
+
+octgrav_mlp* octgrav_mlp_create(const float* params) {
+  g_err.clear();
+  octgrav_mlp* m = new (std::nothrow) octgrav_mlp;
+  if (!m) {
+    fail(OCTGRAV_ENOMEM, "out of host memory");
+    return nullptr;
+  }
+  std::vector<float> zero(kMlpParams, 0.0f);
+  if (m->alloc(&m->P, kMlpParams * 4) || m->alloc(&m->mom1, kMlpParams * 4) ||
+      m->alloc(&m->mom2, kMlpParams * 4) || m->alloc(&m->grad, kMlpParams * 4) ||
+      m->alloc(&m->pk, kPkBytes) || m->alloc(&m->d_loss, 8) ||
+      octgrav_mlp_set_params(m, params ? params : zero.data()) != OCTGRAV_OK) {
+    octgrav_mlp_free(m);
+    return nullptr;
+  }
+  return m;
+}
+
+void octgrav_mlp_free(octgrav_mlp* m) { delete m; }
+
+int octgrav_mlp_set_stream(octgrav_mlp* m, void* hip_stream) {
+  if (!m) return fail(OCTGRAV_EINVAL, "NULL handle");
+  m->stream = (hipStream_t)hip_stream;
+  return OCTGRAV_OK;
+}
+
+int octgrav_mlp_set_params(octgrav_mlp* m, const float* params) {
+  g_err.clear();
+  if (!m || !params) return fail(OCTGRAV_EINVAL, "NULL argument");
+  for (int i = 0; i < kMlpParams; ++i)
+    if (!std::isfinite(params[i])) return fail(OCTGRAV_EINVAL, "non-finite parameter");
+  if (hipMemcpy(m->P, params, kMlpParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(m->mom1, 0, kMlpParams * 4) != hipSuccess ||
+      hipMemset(m->mom2, 0, kMlpParams * 4) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "parameter upload failed");
+  if (launch_mlp_pack((const float*)m->P, m->pk, m->stream) ||
+      hipStreamSynchronize(m->stream) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "pack failed");
+  return OCTGRAV_OK;
+}
+
+int octgrav_mlp_get_params(const octgrav_mlp* m, float* params) {
+  g_err.clear();
+  if (!m || !params) return fail(OCTGRAV_EINVAL, "NULL argument");
+  if (hipStreamSynchronize(m->stream) != hipSuccess ||
+      hipMemcpy(params, m->P, kMlpParams * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "parameter copy-back failed");
+  return OCTGRAV_OK;
+}
+
+int octgrav_mlp_forward(octgrav_mlp* m, const float* x, int64_t b, float* y) {
+  g_err.clear();
+  if (!m) return fail(OCTGRAV_EINVAL, "NULL handle");
+  if (b < 0 || (b > 0 && (!x || !y))) return fail(OCTGRAV_EINVAL, "bad batch arguments");
+  if (launch_mlp_forward(m->pk, x, b, y, nullptr, nullptr, m->stream) ||
+      hipStreamSynchronize(m->stream) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "forward failed");
+  return OCTGRAV_OK;
+}
+
+int octgrav_mlp_loss_grad(octgrav_mlp* m, const float* x, const float* target, int64_t b,
+                          float tau, double* loss, float* grad) {
+  g_err.clear();
+  if (!m || !loss) return fail(OCTGRAV_EINVAL, "NULL argument");
+  if (b < 1 || !x || !target) return fail(OCTGRAV_EINVAL, "bad batch arguments");
+  if (!(tau > 0.0f && tau < 1.0f)) return fail(OCTGRAV_EINVAL, "tau must be in (0, 1)");
+  if (int rc = m->reserve(b)) return rc;
+  float* s = (float*)m->scratch;
+  float *y = s, *dys = y + b, *losss = dys + b, *a1 = losss + b, *a2 = a1 + 64 * b,
+        *dh1 = a2 + 64 * b, *dh2 = dh1 + 64 * b;
+  if (launch_mlp_loss_grad(m->pk, x, target, b, tau, y, a1, a2, dh1, dh2, dys, losss,
+                           (float*)m->grad, (double*)m->d_loss, m->stream) ||
+      hipMemcpyAsync(loss, m->d_loss, 8, hipMemcpyDeviceToHost, m->stream) != hipSuccess ||
+      (grad && hipMemcpyAsync(grad, m->grad, kMlpParams * 4, hipMemcpyDeviceToHost, m->stream) !=
+                   hipSuccess) ||
+      hipStreamSynchronize(m->stream) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "loss/gradient failed");
+  return OCTGRAV_OK;
+}
+
+int octgrav_mlp_adam(octgrav_mlp* m, float lr, float beta1, float beta2, float eps, int32_t step) {
+  g_err.clear();
+  if (!m) return fail(OCTGRAV_EINVAL, "NULL handle");
+  if (step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps > 0.0f))
+    return fail(OCTGRAV_EINVAL, "bad Adam arguments");
+  const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+  if (launch_mlp_adam((float*)m->P, (float*)m->mom1, (float*)m->mom2, (const float*)m->grad, lr,
+                      beta1, beta2, eps, c1, c2, m->stream) ||
+      launch_mlp_pack((const float*)m->P, m->pk, m->stream) ||
+      hipStreamSynchronize(m->stream) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "Adam step failed");
+  return OCTGRAV_OK;
 }
 
 int octgrav_last_timings(octgrav_tree* t, double out[6]) {

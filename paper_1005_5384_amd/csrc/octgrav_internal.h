@@ -37,6 +37,23 @@ struct HostTree {
 bool build_host_tree(const float* pos, const float* mass, int64_t n, int n_leaf, int n_group,
                      HostTree& out, std::string& err);
 
+// ------------------------------------------------------------------ network
+// Learned acceptance criterion: 12 -> 64 -> 64 -> 1 with ReLU.
+constexpr int kMlpIn = 12, kMlpInPad = 16, kMlpH = 64;
+constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH + 1;  // 5057
+// FP32 parameter vector offsets: W1 [64 x 12] row-major, b1, W2 [64 x 64], b2, w3, b3.
+constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kMlpH * kMlpIn, kOffW2 = kOffB1 + kMlpH,
+              kOffB2 = kOffW2 + kMlpH * kMlpH, kOffW3 = kOffB2 + kMlpH, kOffB3 = kOffW3 + kMlpH;
+
+// Packed inference image (one device buffer), byte offsets.
+constexpr int kPkW1 = 0;                              // BF16 [64][16]
+constexpr int kPkW2 = kPkW1 + kMlpH * kMlpInPad * 2;  // BF16 [64][64]
+constexpr int kPkB1 = kPkW2 + kMlpH * kMlpH * 2;      // FP32 [64]
+constexpr int kPkB2 = kPkB1 + kMlpH * 4;              // FP32 [64]
+constexpr int kPkW3 = kPkB2 + kMlpH * 4;              // FP32 [64], BF16-rounded values
+constexpr int kPkB3 = kPkW3 + kMlpH * 4;              // FP32
+constexpr int kPkBytes = kPkB3 + 256;
+
 // ------------------------------------------------------------------ device
 struct DevTree {
   const float* part;     // float4 [n]
@@ -76,6 +93,20 @@ struct WalkBufs {
   // walk's test opens and the test at band_hi2 (squared angle) does not.
   int32_t band;
   float band_hi2;
+  // Learned acceptance criterion (fused wave walk; mlp == NULL: the theta
+  // test).  Candidates the test at mac_lo2 accepts are accepted, those the
+  // test at mac_hi2 opens are opened, the network decides the rest (accept
+  // iff its output <= mac_ltau); a group whose accepted band candidates give
+  // sqrt(sum 10^(2 y)) > mac_budget is walked again with the call's theta.
+  // cnt[g].w = 2 * (band candidates visited) + (1 if the group fell back).
+  const uint8_t* mlp;  // packed network image (mlp_device.h)
+  float mac_lo2, mac_hi2, mac_ltau;
+  double mac_budget;
+  // Decision trace of the learned walks (test export; tr_s == NULL: off):
+  // group g's band candidates at [tr_off[g], tr_off[g + 1]).
+  const int64_t* tr_off;
+  int32_t* tr_c;
+  float* tr_s;
 };
 
 // Kernel launchers (device sources).  mode 0 = count, 1 = write at the
@@ -101,6 +132,17 @@ int launch_direct(const DevTree& T, const int32_t* targets, int64_t nt, float ep
 int launch_mac_labels(const DevTree& T, const WalkBufs& B, const int32_t* groups, int64_t ngs,
                       const int64_t* out_off, const float* acc_direct, float eps, float* feat,
                       float* label, int32_t* gout, int32_t* cout, int64_t npairs, void* stream);
+// Network of the learned criterion: pack FP32 parameters into the BF16
+// inference image; batch forward (a1s / a2s: B x 64 pre-activations, may be
+// NULL); loss + gradient of a batch (scratch arrays B x 64 / B); Adam step.
+int launch_mlp_pack(const float* P, void* pk, void* stream);
+int launch_mlp_forward(const void* pk, const float* x, int64_t B, float* y, float* a1s, float* a2s,
+                       void* stream);
+int launch_mlp_loss_grad(const void* pk, const float* x, const float* tgt, int64_t B, float tau,
+                         float* y, float* a1s, float* a2s, float* dh1s, float* dh2s, float* dys,
+                         float* losss, float* grad, double* loss, void* stream);
+int launch_mlp_adam(float* P, float* m, float* v, const float* g, float lr, float b1, float b2,
+                    float eps, float c1, float c2, void* stream);
 int launch_diag(const DevTree& T, const float* acc, const float* pot, double* part_sums,
                 double* out4, void* stream);
 int64_t scan_scratch_entries(int64_t ng);

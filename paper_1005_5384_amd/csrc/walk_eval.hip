@@ -22,11 +22,23 @@
 // A work item whose frontier outgrows the LDS queue aborts before writing any
 // result and is redone by a fallback kernel whose queues live in global
 // memory, sized so that they cannot overflow.
+//
+// Learned acceptance criterion (LEARNED): candidates the test at theta_lo
+// accepts are accepted, those the test at theta_hi opens are opened, and for
+// the band in between the wave computes the 12 features of its band lanes,
+// stages them in LDS and runs the network on the matrix cores (64 candidates
+// per step); a candidate is accepted iff the predicted log10 error is at most
+// log10 tau_pair.  The accepted band candidates' predicted errors add up
+// (FP64, sqrt of the sum of squares) into the group's budget; a work item
+// whose group exceeds it drops its accumulators and walks again with the
+// call's theta.  Every work item of a group makes the same decisions (same
+// candidates, same network arithmetic, same reduction order).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
 
 #include "device_common.h"
+#include "mlp_device.h"
 #include "octgrav_internal.h"
 
 namespace octgrav {
@@ -133,13 +145,18 @@ struct WItem {
   }
 };
 
-// Walks and evaluates work item w with one wave.  Returns false (uniformly,
-// before writing any result) if the frontier outgrows the queue.
-template <bool PLAIN, typename SH, typename Q>
-__device__ bool walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64_t w,
-                               float th2, float eps2, float* __restrict__ acc,
-                               float* __restrict__ pot, Q q, uint32_t qmask, bool gmem_q,
-                               bool do_eval) {
+enum : int { kOverflow = 0, kDone = 1, kFallBack = 2 };
+
+// Walks and evaluates work item w with one wave.  Returns kOverflow
+// (uniformly, before writing any result) if the frontier outgrows the queue;
+// with LEARNED, kFallBack (nothing written but the trace) if the group's
+// budget is exceeded, *nband = band candidates visited.  cw is the value of
+// cnt[g].w written by a walk with the theta test.
+template <bool PLAIN, bool LEARNED, typename SH, typename Q>
+__device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64_t w,
+                              float th2, float eps2, float* __restrict__ acc,
+                              float* __restrict__ pot, Q q, uint32_t qmask, bool gmem_q,
+                              bool do_eval, int cw, int* nband_out) {
   const int lane = threadIdx.x;
   const int2 wk = reinterpret_cast<const int2*>(T.work)[w];
   const int64_t g = wk.x;
@@ -160,6 +177,12 @@ __device__ bool walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int6
   it.acc4.zero();
 
   const bool exp = B.export_lists && wk.y == 0;
+  // learned criterion state
+  const bool trace = LEARNED && B.tr_s != nullptr && wk.y == 0;
+  const int64_t trb = trace ? B.tr_off[g] : 0, tre = trace ? B.tr_off[g + 1] : 0;
+  const float mtot = LEARNED ? reinterpret_cast<const float4*>(T.mp)[0].w : 0.f;
+  double sum2 = 0.0;
+  int nband = 0;
   const int64_t xcb = exp ? B.c_off[g] : 0, xce = exp ? B.c_off[g + 1] : 0;
   const int64_t xlb = exp ? B.l_off[g] : 0, xle = exp ? B.l_off[g + 1] : 0;
 
@@ -189,7 +212,41 @@ __device__ bool walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int6
       ge = rec[2 * (int64_t)c];
       tp = reinterpret_cast<const int4*>(rec)[2 * (int64_t)c + 1];
     }
-    const bool op = valid && open_cell(gmin, gmax, ge, th2);
+    bool op;
+    if (LEARNED) {
+      const bool olo = valid && open_cell(gmin, gmax, ge, B.mac_lo2);
+      const bool band = olo && !open_cell(gmin, gmax, ge, B.mac_hi2);
+      const uint64_t mB = __ballot(band);
+      bool accb = false;
+      if (mB) {
+        float f[kMlpIn];
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k) f[k] = 0.f;
+        if (band) {
+          const float4* mp = reinterpret_cast<const float4*>(T.mp);
+          mac_features(gmin, gmax, ge, mp[3 * (int64_t)c], mp[3 * (int64_t)c + 1],
+                       mp[3 * (int64_t)c + 2], reinterpret_cast<const float4*>(T.ext)[c], mtot, f);
+        }
+        uint16_t* xs = reinterpret_cast<uint16_t*>(sh.tile);
+        mlp_stage(xs, lane, f);
+        wave_lds_sync();
+        const float yh = mlp_scores64(B.mlp, xs, lane);
+        wave_lds_sync();
+        accb = band && yh <= B.mac_ltau;
+        if (accb) sum2 += exp10(2.0 * (double)yh);
+        if (band && trace) {
+          const int64_t k = trb + nband + rank_below(mB);
+          if (k < tre) {
+            B.tr_c[k] = c;
+            B.tr_s[k] = yh;
+          }
+        }
+        nband += __popcll(mB);
+      }
+      op = olo && !accb;
+    } else {
+      op = valid && open_cell(gmin, gmax, ge, th2);
+    }
     const bool toC = valid && !op, toL = op && tp.y == 0;
     const int nch = (op && tp.y != 0) ? tp.y : 0;
     const uint64_t mC = __ballot(toC), mL = __ballot(toL);
@@ -201,7 +258,7 @@ __device__ bool walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int6
       totN += __popcll(m) << b;
     }
     head += navail;
-    if ((tail + (uint32_t)totN) - head > qmask + 1) return false;
+    if ((tail + (uint32_t)totN) - head > qmask + 1) return kOverflow;
     if (toC) {
       const uint32_t k = ctail + rank_below(mC);
       sh.cring[k & (kRingW - 1)] = c;
@@ -239,9 +296,18 @@ __device__ bool walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int6
     lhead += n;
   }
 
+  if (LEARNED) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum2 += __shfl_xor(sum2, o);
+    if (sqrt(sum2) > B.mac_budget) {
+      *nband_out = nband;
+      return kFallBack;
+    }
+    cw = 2 * nband;
+  }
   if (lane == 0 && wk.y == 0)  // per-group counts; the totals are reduced afterwards
-    reinterpret_cast<int4*>(B.cnt)[g] = make_int4((int)ctail, (int)ltail, (int)it.nsrc, 0);
-  if (!do_eval) return true;
+    reinterpret_cast<int4*>(B.cnt)[g] = make_int4((int)ctail, (int)ltail, (int)it.nsrc, cw);
+  if (!do_eval) return kDone;
 
   // Combine the slices of each target in slice order.
   float* red = reinterpret_cast<float*>(sh.tile);  // [64][8] floats
@@ -279,10 +345,23 @@ __device__ bool walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int6
     if (pot) pot[o] = s[3] + cc[3];
   }
   wave_lds_sync();
-  return true;
+  return kDone;
 }
 
-template <bool PLAIN, int QCAP>
+// One work item, with the theta re-walk of a group over its budget.
+template <bool PLAIN, bool LEARNED, typename SH, typename Q>
+__device__ int walk_eval_one(const DevTree& T, const WalkBufs& B, SH& sh, int64_t w, float th2,
+                             float eps2, float* acc, float* pot, Q q, uint32_t qmask, bool gmem_q,
+                             bool do_eval) {
+  int nb = 0;
+  const int st = walk_eval_item<PLAIN, LEARNED>(T, B, sh, w, th2, eps2, acc, pot, q, qmask, gmem_q,
+                                                do_eval, 0, &nb);
+  if (!LEARNED || st != kFallBack) return st;
+  return walk_eval_item<PLAIN, false>(T, B, sh, w, th2, eps2, acc, pot, q, qmask, gmem_q, do_eval,
+                                      2 * nb + 1, &nb);
+}
+
+template <bool PLAIN, int QCAP, bool LEARNED>
 __global__ __launch_bounds__(kLanes) void walk_eval_kernel(DevTree T, WalkBufs B, float th2,
                                                            float eps2, float* acc, float* pot,
                                                            int do_eval) {
@@ -290,8 +369,8 @@ __global__ __launch_bounds__(kLanes) void walk_eval_kernel(DevTree T, WalkBufs B
   const int64_t w = xcd_slab(blockIdx.x, gridDim.x, T.nw);
   if (w < 0) return;
   const uint32_t qmask = (uint32_t)min(B.lds_qcap, QCAP) - 1;
-  if (!walk_eval_item<PLAIN>(T, B, sh, w, th2, eps2, acc, pot, sh.q, qmask, false,
-                            do_eval != 0) &&
+  if (walk_eval_one<PLAIN, LEARNED>(T, B, sh, w, th2, eps2, acc, pot, sh.q, qmask, false,
+                                    do_eval != 0) == kOverflow &&
       threadIdx.x == 0)
     B.ovf_list[atomicAdd(B.ovf_count, 1)] = (int32_t)w;
 }
@@ -303,7 +382,7 @@ struct GQueue {
   __device__ volatile int32_t& operator[](uint32_t i) const { return p[i]; }
 };
 
-template <bool PLAIN>
+template <bool PLAIN, bool LEARNED>
 __global__ __launch_bounds__(kLanes) void walk_eval_fallback_kernel(DevTree T, WalkBufs B,
                                                                     float th2, float eps2,
                                                                     float* acc, float* pot,
@@ -312,15 +391,20 @@ __global__ __launch_bounds__(kLanes) void walk_eval_fallback_kernel(DevTree T, W
   const int n = *B.ovf_count;
   GQueue q{B.gq + (int64_t)blockIdx.x * B.gq_cap};
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const bool ok = walk_eval_item<PLAIN>(T, B, sh, B.ovf_list[i], th2, eps2, acc, pot, q,
-                                          (uint32_t)(B.gq_cap - 1), true, do_eval != 0);
-    if (!ok && threadIdx.x == 0) atomicOr(reinterpret_cast<unsigned long long*>(&B.tot[5]), 1ull);
+    const int st = walk_eval_one<PLAIN, LEARNED>(T, B, sh, B.ovf_list[i], th2, eps2, acc, pot, q,
+                                                 (uint32_t)(B.gq_cap - 1), true, do_eval != 0);
+    if (st == kOverflow && threadIdx.x == 0)
+      atomicOr(reinterpret_cast<unsigned long long*>(&B.tot[5]), 1ull);
   }
 }
 
 __global__ void fused_init_kernel(WalkBufs B) {
   if (threadIdx.x < 8) B.tot[threadIdx.x] = 0;
-  if (threadIdx.x == 0) *B.ovf_count = 0;
+  if (threadIdx.x == 0) {
+    *B.ovf_count = 0;
+    B.c_off[0] = 0;  // base of an offsets scan of the counts this walk writes
+    B.l_off[0] = 0;
+  }
 }
 
 }  // namespace
@@ -335,15 +419,22 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
   // which grows like theta^-3: 1024 entries cover theta >= 0.45 on Plummer
   // spheres of 2^20 (peak ~740 at 0.5), 4096 the smaller angles.  Work items
   // that still overflow go to the fallback kernel.
-  const bool wide = theta < 0.45f;
-  auto go = [&](auto plain_tag) {
-    constexpr bool P = decltype(plain_tag)::value;
-    if (wide) walk_eval_kernel<P, 4096><<<grid, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
-    else walk_eval_kernel<P, 1024><<<grid, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
-    walk_eval_fallback_kernel<P><<<B.gq_waves, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
+  // The learned walk opens no more than the theta_lo walk does.
+  const bool learned = B.mlp != nullptr;
+  const bool wide = theta < 0.45f || learned;
+  auto go = [&](auto plain_tag, auto learned_tag) {
+    constexpr bool P = decltype(plain_tag)::value, L = decltype(learned_tag)::value;
+    if (wide) walk_eval_kernel<P, 4096, L><<<grid, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
+    else walk_eval_kernel<P, 1024, L><<<grid, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
+    walk_eval_fallback_kernel<P, L><<<B.gq_waves, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
   };
-  if (plain) go(std::true_type{});
-  else go(std::false_type{});
+  if (learned) {
+    if (plain) go(std::true_type{}, std::true_type{});
+    else go(std::false_type{}, std::true_type{});
+  } else {
+    if (plain) go(std::true_type{}, std::false_type{});
+    else go(std::false_type{}, std::false_type{});
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

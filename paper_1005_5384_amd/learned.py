@@ -1,0 +1,135 @@
+"""Training and calibration of the learned acceptance criterion.
+
+Everything numerical runs in the library's kernels: labels from the GPU
+direct sum and the per-pair label kernel, training by the library's
+forward / backward / Adam kernels.  This module only shuffles batches and
+drives the loops.
+
+    python -m paper_1005_5384_amd.learned train --out params.npy
+"""
+from __future__ import annotations
+
+import argparse
+import time
+
+import numpy as np
+
+from . import octgrav as og
+from . import workloads as W
+
+THETA_LO, THETA_HI = 0.3, 1.0
+PINBALL_TAU = 0.9
+
+
+def collect(pos, mass, eps, n_leaf=16, n_group=64, stride=1, cap=1 << 23):
+    """(features [k,12], targets log10(max(e, 1e-12)) [k]) of the band pairs
+    of one particle set (torch CUDA tensors)."""
+    import torch
+    T = og.Tree(pos, mass, n_leaf, n_group)
+    acc, _ = T.direct(eps)
+    feat, lab, _, _ = T.mac_collect(eps, acc, THETA_LO, THETA_HI, stride=stride, cap=cap)
+    y = torch.log10(torch.clamp(lab, min=1e-12))
+    return feat.clone(), y.clone()
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, output bias at a typical log10 error."""
+    rng = np.random.default_rng(seed)
+    P = np.zeros(og.N_PARAMS, np.float32)
+    P[0:768] = rng.normal(0, np.sqrt(2 / 12), 768)
+    P[832:4928] = rng.normal(0, np.sqrt(2 / 64), 4096)
+    P[4992:5056] = rng.normal(0, np.sqrt(1 / 64), 64)
+    P[5056] = -4.0
+    return P
+
+
+def train(x, y, epochs=40, batch=4096, lr=1e-3, tau=PINBALL_TAU, seed=0, params=None,
+          lr_final=1e-4, log=None):
+    """Trains a network on (x, y) (CUDA tensors) with mini-batch Adam and a
+    geometric learning-rate decay; returns the Mlp."""
+    import torch
+    m = og.Mlp(init_params(seed) if params is None else params)
+    n = x.shape[0]
+    gen = torch.Generator().manual_seed(seed)
+    nb = max(1, n // batch)
+    total = epochs * nb
+    step = 0
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=gen).cuda()
+        run = 0.0
+        for b in range(nb):
+            idx = perm[b * batch:(b + 1) * batch]
+            loss, _ = m.loss_grad(x[idx], y[idx], tau, want_grad=False)
+            run += loss
+            step += 1
+            m.adam(step, lr=lr * (lr_final / lr) ** (step / total))
+        if log:
+            log(f"epoch {ep + 1}/{epochs} loss {run / nb:.5f}")
+    return m
+
+
+def training_data(stride=1, log=None):
+    import torch
+    xs, ys = [], []
+    for k in range(len(W.TRAINING_SETS)):
+        t0 = time.time()
+        pos, mass = W.make_training(k)
+        x, y = collect(pos, mass, W.TRAINING_EPS, stride=stride)
+        xs.append(x)
+        ys.append(y)
+        if log:
+            log(f"set {k}: {x.shape[0]} pairs in {time.time() - t0:.1f} s")
+    return torch.cat(xs), torch.cat(ys)
+
+
+# ------------------------------------------------------------------ calibration
+
+def p99_error(T, eps, sample, ref_acc, theta):
+    """99th percentile of |a - a_ref| / |a_ref| over the sampled particles."""
+    acc, _ = T.forces(theta, eps, with_pot=False)
+    a = acc[sample].double()
+    r = ref_acc.double()
+    e = (a - r).norm(dim=1) / r.norm(dim=1)
+    return float(np.quantile(e.cpu().numpy(), 0.99))
+
+
+def bisect(f, lo, hi, target, increasing, iters=12, rtol=0.02):
+    """x in [lo, hi] with f(x) ~ target (f monotone; `increasing` in x).
+    Returns (x, f(x)) of the last point on the safe side of the target."""
+    best = None
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        v = f(mid)
+        if v <= target:
+            best = (mid, v)
+        if abs(v - target) <= rtol * target and v <= target:
+            break
+        if (v < target) == increasing:
+            lo = mid
+        else:
+            hi = mid
+    if best is None:
+        x = lo if increasing else hi
+        best = (x, f(x))
+    return best
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    tr = sub.add_parser("train")
+    tr.add_argument("--out", required=True)
+    tr.add_argument("--epochs", type=int, default=40)
+    tr.add_argument("--stride", type=int, default=1)
+    tr.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args()
+    if a.cmd == "train":
+        x, y = training_data(a.stride, log=lambda s: print(s, flush=True))
+        t0 = time.time()
+        m = train(x, y, epochs=a.epochs, seed=a.seed, log=lambda s: print(s, flush=True))
+        print(f"trained on {x.shape[0]} pairs in {time.time() - t0:.1f} s", flush=True)
+        np.save(a.out, m.params())
+
+
+if __name__ == "__main__":
+    main()

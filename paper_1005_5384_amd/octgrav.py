@@ -47,7 +47,12 @@ EXPORTED = ["octgrav_build_tree", "octgrav_build_tree_ex", "octgrav_forces", "oc
             "octgrav_free", "octgrav_last_error", "octgrav_set_stream", "octgrav_tree_stats",
             "octgrav_export_tree", "octgrav_lists", "octgrav_lists_ex", "octgrav_diagnostics",
             "octgrav_last_counts", "octgrav_direct", "octgrav_mac_collect",
-            "octgrav_last_timings"]
+            "octgrav_last_timings", "octgrav_mlp_create", "octgrav_mlp_free",
+            "octgrav_mlp_set_stream", "octgrav_mlp_set_params", "octgrav_mlp_get_params",
+            "octgrav_mlp_forward", "octgrav_mlp_loss_grad", "octgrav_mlp_adam", "octgrav_set_mac",
+            "octgrav_mac_stats", "octgrav_mac_trace"]
+
+N_PARAMS = 12 * 64 + 64 + 64 * 64 + 64 + 64 + 1  # 5057
 
 
 def lib():
@@ -84,6 +89,19 @@ def lib():
         L.octgrav_direct.argtypes = [vp, f32, vp, i64, vp, vp]
         L.octgrav_mac_collect.argtypes = [vp, f32, f32, f32, vp, i32, vp, vp, vp, vp, i64,
                                           C.POINTER(i64)]
+        L.octgrav_mlp_create.restype = vp
+        L.octgrav_mlp_create.argtypes = [vp]
+        L.octgrav_mlp_free.argtypes = [vp]
+        L.octgrav_mlp_free.restype = None
+        L.octgrav_mlp_set_stream.argtypes = [vp, vp]
+        L.octgrav_mlp_set_params.argtypes = [vp, vp]
+        L.octgrav_mlp_get_params.argtypes = [vp, vp]
+        L.octgrav_mlp_forward.argtypes = [vp, vp, i64, vp]
+        L.octgrav_mlp_loss_grad.argtypes = [vp, vp, vp, i64, f32, vp, vp]
+        L.octgrav_mlp_adam.argtypes = [vp, f32, f32, f32, f32, i32]
+        L.octgrav_set_mac.argtypes = [vp, vp, f32, f32, f32, f32]
+        L.octgrav_mac_stats.argtypes = [vp, vp]
+        L.octgrav_mac_trace.argtypes = [vp, f32, vp, vp, vp, i64, C.POINTER(i64), vp]
         _lib = L
     return _lib
 
@@ -204,6 +222,32 @@ class Tree:
         k = n.value
         return feat[:k], lab[:k], gid[:k], cid[:k]
 
+    def set_mac(self, mlp=None, theta_lo=0.3, theta_hi=1.0, tau_pair=1e-3, budget=float("inf")):
+        """Learned acceptance criterion with network `mlp` (an Mlp), or the
+        opening angle alone (mlp=None)."""
+        _check(lib().octgrav_set_mac(self._h, None if mlp is None else mlp._h, float(theta_lo),
+                                     float(theta_hi), float(tau_pair), float(budget)))
+
+    def mac_stats(self):
+        out = np.zeros(2, np.int64)
+        _check(lib().octgrav_mac_stats(self._h, _ptr(out)))
+        return dict(band=int(out[0]), fell_back=int(out[1]))
+
+    def mac_trace(self, theta):
+        """(off [ng+1], cells, scores, fell_back [ng]) of the learned walks."""
+        self._bind_stream()
+        ng = self.stats["n_groups"]
+        off = np.zeros(ng + 1, np.int64)
+        fb = np.zeros(ng, np.int32)
+        n = C.c_int64()
+        _check(lib().octgrav_mac_trace(self._h, float(theta), _ptr(off), None, None, 0,
+                                       C.byref(n), _ptr(fb)))
+        cells = np.zeros(max(1, n.value), np.int32)
+        scores = np.zeros(max(1, n.value), np.float32)
+        _check(lib().octgrav_mac_trace(self._h, float(theta), _ptr(off), _ptr(cells),
+                                       _ptr(scores), cells.size, C.byref(n), _ptr(fb)))
+        return off, cells[:n.value], scores[:n.value], fb
+
     def export(self):
         s = self.stats
         n, nc, ng = s["n"], s["n_cells"], s["n_groups"]
@@ -232,3 +276,75 @@ class Tree:
         _check(lib().octgrav_last_timings(self._h, _ptr(out)))
         return dict(zip(("walk_count", "offsets", "walk_write", "eval", "diag", "total"),
                         out.tolist()))
+
+
+class Mlp:
+    """The learned criterion's network on the device (FP32 master parameters,
+    Adam moments, BF16 inference image)."""
+
+    def __init__(self, params=None):
+        p = None
+        if params is not None:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            if p.size != N_PARAMS:
+                raise ValueError(f"need {N_PARAMS} parameters")
+        h = lib().octgrav_mlp_create(_ptr(p))
+        if not h:
+            raise OctgravError(ENOMEM, last_error())
+        self._h = C.c_void_p(h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.octgrav_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _bind_stream(self):
+        import torch
+        _check(lib().octgrav_mlp_set_stream(self._h,
+                                            C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != N_PARAMS:
+            raise ValueError(f"need {N_PARAMS} parameters")
+        self._bind_stream()
+        _check(lib().octgrav_mlp_set_params(self._h, _ptr(p)))
+
+    def params(self):
+        p = np.zeros(N_PARAMS, np.float32)
+        self._bind_stream()
+        _check(lib().octgrav_mlp_get_params(self._h, _ptr(p)))
+        return p
+
+    def forward(self, x):
+        """x: float32 CUDA tensor [b, 12] -> y [b]."""
+        import torch
+        x = x.to(dtype=torch.float32).contiguous()
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        if x.shape[0] == 0:
+            return y
+        self._bind_stream()
+        _check(lib().octgrav_mlp_forward(self._h, C.c_void_p(x.data_ptr()), x.shape[0],
+                                         C.c_void_p(y.data_ptr())))
+        return y
+
+    def loss_grad(self, x, target, tau=0.9, want_grad=True):
+        """(mean pinball loss, gradient [5057] numpy or None)."""
+        import torch
+        x = x.to(dtype=torch.float32).contiguous()
+        target = target.to(dtype=torch.float32).contiguous()
+        loss = np.zeros(1)
+        g = np.zeros(N_PARAMS, np.float32) if want_grad else None
+        self._bind_stream()
+        _check(lib().octgrav_mlp_loss_grad(self._h, C.c_void_p(x.data_ptr()),
+                                           C.c_void_p(target.data_ptr()), x.shape[0], float(tau),
+                                           _ptr(loss), _ptr(g)))
+        return float(loss[0]), g
+
+    def adam(self, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._bind_stream()
+        _check(lib().octgrav_mlp_adam(self._h, float(lr), float(beta1), float(beta2), float(eps),
+                                      int(step)))

@@ -167,6 +167,26 @@ WORKLOADS = {
 }
 
 
+# Training sets of the learned acceptance criterion: a Plummer sphere and
+# static two-Plummer configurations at three separations (scale radii), all
+# 2^18 particles, softened as the 2^20 Plummer workload.
+TRAINING_SETS = (
+    dict(gen="plummer", n=1 << 18, seed=104),
+    dict(gen="two_plummer", n=1 << 18, seed=105, separation=2.0),
+    dict(gen="two_plummer", n=1 << 18, seed=106, separation=4.0),
+    dict(gen="two_plummer", n=1 << 18, seed=107, separation=8.0),
+)
+TRAINING_EPS = 1e-3
+
+
+def make_training(k: int):
+    """Positions and masses of training set k."""
+    w = dict(TRAINING_SETS[k])
+    gen = {"plummer": plummer, "two_plummer": two_plummer}[w.pop("gen")]
+    n, seed = w.pop("n"), w.pop("seed")
+    return gen(n, seed, **w)
+
+
 def make(name: str, n: int | None = None):
     """Positions [n,3] f32 and masses [n] f32 of a named workload."""
     w = WORKLOADS[name]

@@ -348,3 +348,15 @@ def test_diagnostics_direct():
     assert np.isclose(Wp, 0.5 * np.sum(m.astype(np.float64) * p), rtol=1e-14)
     # Untruncated, unsoftened Plummer: W = -3 pi / 32; N = 1024 is near it.
     assert abs(Wp / (-3 * np.pi / 32) - 1) < 0.05
+
+
+def test_forces_from_given_lists_equal_own_walk():
+    pos, m = W.plummer(2048, 77)
+    T = oracle.Tree(pos, m, 8, 32)
+    a, p = T.forces(0.6, 0.01)
+    b, q = T.forces_lists(T.lists(0.6), 0.01)
+    assert np.array_equal(a, b) and np.array_equal(p, q)
+    # lists of another angle give that angle's forces
+    c, _ = T.forces_lists(T.lists(0.4), 0.01)
+    d, _ = T.forces(0.4, 0.01)
+    assert np.array_equal(c, d)
