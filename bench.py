@@ -65,6 +65,66 @@ def cpu_baseline(pos, m, w, gpu_acc, gpu_pot, n_groups_sample=1024):
     }
 
 
+def learned_vs_theta(T, w, steps, band=(0.3, 1.0), beta=8.0, target=1e-3):
+    """The learned acceptance criterion against the opening angle at equal
+    p99 relative force error (against the GPU direct sum on the 4096-particle
+    sample): theta* by bisection, then tau_pair (budget = beta * tau_pair) by
+    bisection in log tau, then both timed over `steps` force calls."""
+    import torch
+    from paper_1005_5384_amd import learned as L
+    from paper_1005_5384_amd import octgrav as og
+    from paper_1005_5384_amd import workloads as W
+    eps = w["eps"]
+    smp = W.sample_indices(T.n, w.get("sample", 4096), w.get("sample_seed", 4096))
+    ref, _ = T.direct(eps, smp)
+    sm = torch.as_tensor(smp, device="cuda")
+    acc = torch.empty((T.n, 3), dtype=torch.float32, device="cuda")
+
+    def p99(theta):
+        return L.p99_error(T, eps, sm, ref, theta)
+
+    def timed(theta):
+        T.forces(theta, eps, acc=acc, with_pot=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            T.forces(theta, eps, acc=acc, with_pot=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    T.set_mac(None)
+    th, e_th = L.bisect(p99, 0.3, 1.0, target, increasing=True)
+    t_th = timed(th)
+    c_th = T.last_counts()
+    log(f"bench: theta* {th:.4f} p99 {e_th:.3e} {t_th * 1e3:.3f} ms")
+    net = og.Mlp(L.load_params())
+
+    def p99_tau(lt):
+        T.set_mac(net, band[0], band[1], 10.0 ** lt, beta * 10.0 ** lt)
+        return p99(th)
+    lt, e_l = L.bisect(p99_tau, -6.0, -1.0, target, increasing=True)
+    tau = 10.0 ** lt
+    T.set_mac(net, band[0], band[1], tau, beta * tau)
+    t_l = timed(th)
+    c_l = T.last_counts()
+    st = T.mac_stats()
+    T.set_mac(None)
+    log(f"bench: learned tau {tau:.3e} p99 {e_l:.3e} {t_l * 1e3:.3f} ms")
+    n = T.n
+    return {
+        "target_p99": target, "sample": len(smp), "reference": "GPU FP32-compensated direct sum",
+        "theta": {"theta_star": th, "p99": e_th, "particles_per_s": n / t_th, "ms": t_th * 1e3,
+                  "pc_per_particle": c_th["n_pc"] / n, "pp_per_particle": c_th["n_pp"] / n},
+        "learned": {"theta_lo": band[0], "theta_hi": band[1], "tau_pair": tau,
+                    "budget": beta * tau, "fallback_theta": th, "p99": e_l,
+                    "particles_per_s": n / t_l, "ms": t_l * 1e3,
+                    "pc_per_particle": c_l["n_pc"] / n, "pp_per_particle": c_l["n_pp"] / n,
+                    "band_scored": st["band"], "groups_fell_back": st["fell_back"],
+                    "groups": T.stats["n_groups"]},
+        "speedup": t_th / t_l,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,10 +135,15 @@ def main():
     ap.add_argument("--path", default=None, choices=["two_pass", "fused_block", "fused_wave"],
                     help="force one implementation path (default: the library's choice for theta)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-criterion vs theta comparison at equal p99 error")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of the bench: time a plain device copy of this many bytes "
+                         "(the reference for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+              "(one process drives one GPU; the path shards by groups over a replicated tree)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -86,6 +151,20 @@ def main():
     from paper_1005_5384_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_bytes:
+        nb = args.copy_bytes // 16 * 16
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"copy_bytes": nb, "ms": dt * 1e3, "read_plus_write_GBps": 2 * nb / dt / 1e9}))
+        return
     w = W.WORKLOADS[args.workload]
     log(f"bench: generating {args.workload} n={w['n']}")
     pos, m = W.make(args.workload)
@@ -152,6 +231,9 @@ def main():
         "host_build_upload_s": t_build,
         "tree": T.stats,
     }
+    if not args.no_learned:
+        log("bench: learned criterion vs theta at p99 1e-3 ...")
+        out["learned_vs_theta"] = learned_vs_theta(T, w, args.steps)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle) ...")
         a = acc.double().cpu().numpy()

@@ -10,6 +10,7 @@ drives the loops.
 from __future__ import annotations
 
 import argparse
+import os
 import time
 
 import numpy as np
@@ -19,6 +20,16 @@ from . import workloads as W
 
 THETA_LO, THETA_HI = 0.3, 1.0
 PINBALL_TAU = 0.9
+PARAMS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
+                           "learned_mac_params.npy")
+
+
+def load_params(path: str = PARAMS_PATH) -> np.ndarray:
+    """The trained network's 5057 FP32 parameters (written by `train`)."""
+    P = np.load(path, allow_pickle=False)
+    if P.dtype != np.float32 or P.shape != (og.N_PARAMS,):
+        raise ValueError(f"{path}: expected {og.N_PARAMS} float32 parameters")
+    return P
 
 
 def collect(pos, mass, eps, n_leaf=16, n_group=64, stride=1, cap=1 << 23):
