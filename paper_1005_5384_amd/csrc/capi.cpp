@@ -174,16 +174,31 @@ struct octgrav_tree {
       std::memcpy(&wrec[8 * c], &geo_dev[4 * c], 16);
       std::memcpy(&wrec[8 * c + 4], &h.topo[4 * c], 16);
     }
-    // Feature inputs of the learned criterion: FP32 tight-box extents and
-    // the level of each cell; and the inverse permutation for direct sums.
-    std::vector<float> ext((size_t)nc * 4);
+    // The cell-only parts of the learned criterion's features, in FP32 from
+    // the FP32 images: tight-box extents, log2(1 + depth) / log2(22) | mass,
+    // Frobenius norm of Q, |com - boundary centre|.  And the inverse
+    // permutation for direct sums.
+    std::vector<float> fcell((size_t)nc * 8);
     for (int64_t c = 0; c < nc; ++c) {
-      for (int k = 0; k < 3; ++k) ext[4 * c + k] = (float)(h.box[6 * c + 3 + k] - h.box[6 * c + k]);
-      ext[4 * c + 3] = (float)h.depth[c];
+      float* o = &fcell[8 * c];
+      const float* m = &h.mp[12 * c];
+      const float* gc = &h.geo[4 * c];
+      for (int k = 0; k < 3; ++k) o[k] = (float)(h.box[6 * c + 3 + k] - h.box[6 * c + k]);
+      o[3] = std::log2(1.0f + (float)h.depth[c]) / std::log2(22.0f);
+      o[4] = m[3];
+      o[5] = std::sqrt((m[4] * m[4] + m[5] * m[5] + m[6] * m[6]) +
+                       2.0f * (m[7] * m[7] + m[8] * m[8] + m[9] * m[9]));
+      float s2 = 0.0f;
+      for (int k = 0; k < 3; ++k) {
+        const float d = m[k] - gc[k];
+        s2 += d * d;
+      }
+      o[6] = std::sqrt(s2);
+      o[7] = 0.0f;
     }
     std::vector<int32_t> iperm(n);
     for (int64_t i = 0; i < n; ++i) iperm[h.perm[i]] = (int32_t)i;
-    if ((rc = upload(ext, &dt.ext)) || (rc = upload(iperm, &dt.iperm))) return rc;
+    if ((rc = upload(fcell, &dt.fcell)) || (rc = upload(iperm, &dt.iperm))) return rc;
     if ((rc = upload(h.part, &dt.part)) || (rc = upload(h.perm, &dt.perm)) ||
         (rc = upload(h.topo, &dt.topo)) || (rc = upload(geo_dev, &dt.geo)) ||
         (rc = upload(wrec, &dt.wrec)) ||
@@ -205,6 +220,8 @@ struct octgrav_tree {
     wb.ovf_list = (int32_t*)p;
     if ((rc = dalloc(&p, 4))) return rc;
     wb.ovf_count = (int32_t*)p;
+    if ((rc = dalloc(&p, 8 * 64 * 4))) return rc;
+    wb.wctr = (int32_t*)p;
     // Fallback frontier queues: a breadth-first FIFO never holds more than
     // two consecutive levels, hence at most twice the widest level.
     int64_t cap = 64;

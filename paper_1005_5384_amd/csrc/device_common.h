@@ -112,37 +112,52 @@ struct Sum4 {
 };
 
 // The 12 input features of the learned acceptance criterion for candidate
-// cell c seen from a group's tight box, in FP32 (see the learned-MAC notes in
-// mlp.hip): d/l, log10(M/M_tot)/3, |Q|_F/(M l^2), log2(1 + r_g/l), cell
-// extents / l, log2(1 + group extents / l), log2(1 + depth)/log2(22),
-// |com - boundary centre| / l.  geo.w may carry the leaf sign bit.
-__device__ __forceinline__ void mac_features(float4 gmin, float4 gmax, float4 geo, float4 m0,
-                                             float4 m1, float4 m2, float4 ext, float mtot,
-                                             float* f) {
+// cell c seen from a group's tight box, in FP32: d/l, log10(M/M_tot)/3,
+// |Q|_F/(M l^2), log2(1 + r_g/l), cell extents / l, log2(1 + group
+// extents / l), log2(1 + depth)/log2(22), |com - boundary centre| / l.
+// The group's part (MacGroup) is computed once per group and the cell's
+// part (fc0 = extents, depth term; fc1 = M, |Q|_F, |com - centre|) once per
+// cell on the host; the rest uses the hardware reciprocal, square root and
+// log2 (about 1 ulp each: the features are rounded to BF16 for the network).
+struct MacGroup {
+  float4 gmin, gmax;
+  float gx, gy, gz, rg, rmtot;
+};
+
+__device__ __forceinline__ MacGroup mac_group(float4 gmin, float4 gmax, float mtot) {
 #pragma clang fp contract(off)
-  const float l = fabsf(geo.w);
-  const float tx = fmaxf(fmaxf(gmin.x - geo.x, geo.x - gmax.x), 0.0f);
-  const float ty = fmaxf(fmaxf(gmin.y - geo.y, geo.y - gmax.y), 0.0f);
-  const float tz = fmaxf(fmaxf(gmin.z - geo.z, geo.z - gmax.z), 0.0f);
-  const float d = sqrtf((tx * tx + ty * ty) + tz * tz);
-  const float M = m0.w;
-  const float qn = sqrtf((m1.x * m1.x + m1.y * m1.y + m1.z * m1.z) +
-                         2.0f * (m1.w * m1.w + m2.x * m2.x + m2.y * m2.y));
-  const float gx = gmax.x - gmin.x, gy = gmax.y - gmin.y, gz = gmax.z - gmin.z;
-  const float rg = 0.5f * sqrtf((gx * gx + gy * gy) + gz * gz);
-  f[0] = d / l;
-  f[1] = log10f(M / mtot) / 3.0f;
-  f[2] = qn / (M * l * l);
-  f[3] = log2f(1.0f + rg / l);
-  f[4] = ext.x / l;
-  f[5] = ext.y / l;
-  f[6] = ext.z / l;
-  f[7] = log2f(1.0f + gx / l);
-  f[8] = log2f(1.0f + gy / l);
-  f[9] = log2f(1.0f + gz / l);
-  f[10] = log2f(1.0f + ext.w) / log2f(22.0f);
-  const float cx = m0.x - geo.x, cy = m0.y - geo.y, cz = m0.z - geo.z;
-  f[11] = sqrtf((cx * cx + cy * cy) + cz * cz) / l;
+  MacGroup G;
+  G.gmin = gmin;
+  G.gmax = gmax;
+  G.gx = gmax.x - gmin.x;
+  G.gy = gmax.y - gmin.y;
+  G.gz = gmax.z - gmin.z;
+  G.rg = 0.5f * __builtin_amdgcn_sqrtf((G.gx * G.gx + G.gy * G.gy) + G.gz * G.gz);
+  G.rmtot = __builtin_amdgcn_rcpf(mtot);
+  return G;
+}
+
+__device__ __forceinline__ void mac_features(const MacGroup& G, float4 geo, float4 fc0,
+                                             float4 fc1, float* f) {
+#pragma clang fp contract(off)
+  const float l = fabsf(geo.w), rl = __builtin_amdgcn_rcpf(l);
+  const float tx = fmaxf(fmaxf(G.gmin.x - geo.x, geo.x - G.gmax.x), 0.0f);
+  const float ty = fmaxf(fmaxf(G.gmin.y - geo.y, geo.y - G.gmax.y), 0.0f);
+  const float tz = fmaxf(fmaxf(G.gmin.z - geo.z, geo.z - G.gmax.z), 0.0f);
+  const float d = __builtin_amdgcn_sqrtf((tx * tx + ty * ty) + tz * tz);
+  constexpr float kLog10_2_over_3 = 0.100343331887994f;  // log10(2) / 3
+  f[0] = d * rl;
+  f[1] = __builtin_amdgcn_logf(fc1.x * G.rmtot) * kLog10_2_over_3;
+  f[2] = fc1.y * __builtin_amdgcn_rcpf(fc1.x * l * l);
+  f[3] = __builtin_amdgcn_logf(1.0f + G.rg * rl);
+  f[4] = fc0.x * rl;
+  f[5] = fc0.y * rl;
+  f[6] = fc0.z * rl;
+  f[7] = __builtin_amdgcn_logf(1.0f + G.gx * rl);
+  f[8] = __builtin_amdgcn_logf(1.0f + G.gy * rl);
+  f[9] = __builtin_amdgcn_logf(1.0f + G.gz * rl);
+  f[10] = fc0.w;
+  f[11] = fc1.z * rl;
 }
 
 // Every S-th entry of an LDS tile, starting at `first`, two at a time so the

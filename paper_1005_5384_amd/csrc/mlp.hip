@@ -27,7 +27,7 @@ __global__ void mlp_pack_kernel(const float* __restrict__ P, uint8_t* __restrict
   uint16_t* w2 = reinterpret_cast<uint16_t*>(pk + kPkW2);
   float* b1 = reinterpret_cast<float*>(pk + kPkB1);
   float* b2 = reinterpret_cast<float*>(pk + kPkB2);
-  float* w3 = reinterpret_cast<float*>(pk + kPkW3);
+  uint16_t* w3 = reinterpret_cast<uint16_t*>(pk + kPkW3);
   for (int i = threadIdx.x; i < kMlpH * kMlpInPad; i += blockDim.x) {
     const int j = i / kMlpInPad, k = i % kMlpInPad;
     w1[i] = k < kMlpIn ? (uint16_t)bf16_bits(P[kOffW1 + j * kMlpIn + k]) : (uint16_t)0;
@@ -36,7 +36,7 @@ __global__ void mlp_pack_kernel(const float* __restrict__ P, uint8_t* __restrict
   for (int i = threadIdx.x; i < kMlpH; i += blockDim.x) {
     b1[i] = P[kOffB1 + i];
     b2[i] = P[kOffB2 + i];
-    w3[i] = bf16_round(P[kOffW3 + i]);
+    w3[i] = (uint16_t)bf16_bits(P[kOffW3 + i]);
   }
   if (threadIdx.x == 0) *reinterpret_cast<float*>(pk + kPkB3) = P[kOffB3];
 }
@@ -52,13 +52,14 @@ __global__ __launch_bounds__(64) void mlp_forward_kernel(const uint8_t* __restri
   float f[kMlpIn];
 #pragma unroll
   for (int k = 0; k < kMlpIn; ++k) f[k] = smp < B ? x[smp * kMlpIn + k] : 0.f;
-  mlp_stage(xs, lane, f);
+  mlp_stage(xs, kMlpInPad, lane, f);
   __syncthreads();
   v4f32 a1[4], a2[4];
   const int quad = lane >> 4;
+  const MlpView V = mlp_global(pk);
 #pragma unroll 1
   for (int t = 0; t < 4; ++t) {
-    const float s = mlp_tile(pk, xs, t, lane, a1, a2);
+    const float s = mlp_tile(V, xs, kMlpInPad, t, lane, a1, a2);
     const int64_t st = base + 16 * t + (lane & 15);
     if (st < B && a1s) {
 #pragma unroll
@@ -83,14 +84,14 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const uint16_t* w2 = reinterpret_cast<const uint16_t*>(pk + kPkW2);
-  const float* w3 = reinterpret_cast<const float*>(pk + kPkW3);
+  const uint16_t* w3 = reinterpret_cast<const uint16_t*>(pk + kPkW3);
   const float r = tgt[b] - y[b];
   losss[b] = r > 0.f ? tau * r : (tau - 1.f) * r;
   const float dy = (r > 0.f ? -tau : 1.f - tau) / (float)B;
   dys[b] = dy;
   float d2r[kMlpH];
   for (int k = 0; k < kMlpH; ++k) {
-    const float d = a2s[b * kMlpH + k] > 0.f ? dy * w3[k] : 0.f;
+    const float d = a2s[b * kMlpH + k] > 0.f ? dy * __uint_as_float((uint32_t)w3[k] << 16) : 0.f;
     dh2s[b * kMlpH + k] = d;
     d2r[k] = bf16_round(d);
   }

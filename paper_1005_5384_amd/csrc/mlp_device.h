@@ -3,7 +3,7 @@
 //
 // Arithmetic: inputs, weights and hidden activations are rounded to BF16
 // (round to nearest even) before every product; products accumulate in FP32
-// (v_mfma_f32_16x16x16_bf16, exact BF16 x BF16 products); biases are FP32.
+// (exact BF16 x BF16 products on the matrix cores); biases are FP32.
 //
 // Layout: the layers are computed transposed, H^T = W X^T, so that a layer's
 // 16x16 output blocks are already the next layer's B operands.  For the
@@ -11,11 +11,17 @@
 //   A: row l%16, columns 4(l/16) .. 4(l/16)+3        (4 BF16)
 //   B: rows 4(l/16) .. 4(l/16)+3, column l%16        (4 BF16)
 //   D: rows 4(l/16) .. 4(l/16)+3, column l%16        (4 FP32)
-// Rows of A are hidden units, columns of B are samples: a 16-sample tile
-// needs 4 MFMAs for layer 1 (K = 16: 12 features + 4 zero columns) and 16 for
-// layer 2 (K = 64 as 4 blocks); layer 3 is a dot product folded across the
-// four lane groups.  Weights are read straight from their row-major BF16
-// images (8-byte loads), biases and w3 as float4 per lane.
+// and for the 16x16x32 BF16 MFMA (gfx950) the same with 8 consecutive
+// columns / rows 8(l/16) .. 8(l/16)+7.  Rows of A are hidden units, columns
+// of B are samples.  Layer 1 (K = 16: 12 features + 4 zero columns) takes 4
+// 16x16x16 MFMAs per 16-sample tile.  Layer 2 (K = 64) takes 8 16x16x32
+// MFMAs: its B operand for K block q is the lane's two layer-1 output
+// blocks 2q and 2q+1 side by side, i.e. the contraction index runs over the
+// hidden units in the order 16(2q) + 4(l/16) + 0..3, 16(2q+1) + 4(l/16) +
+// 0..3; the A operand reads W2's columns in that same order (two 8-byte
+// loads per lane).  Layer 3 is two more 16x16x32 MFMAs whose A operand
+// repeats w3 in all 16 rows, so every lane receives the output of its own
+// column (sample) without a shuffle.  Biases are read as float4 per lane.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,6 +36,8 @@ namespace dev {
 
 typedef short v4s16 __attribute__((ext_vector_type(4)));
 typedef float v4f32 __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest even (finite inputs).
 __device__ __forceinline__ uint32_t bf16_bits(float f) {
@@ -39,13 +47,13 @@ __device__ __forceinline__ uint32_t bf16_bits(float f) {
 }
 __device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(bf16_bits(f) << 16); }
 
-__device__ __forceinline__ v4s16 pack4(float a, float b, float c, float d) {
-  v4s16 r;
-  r[0] = (short)bf16_bits(a);
-  r[1] = (short)bf16_bits(b);
-  r[2] = (short)bf16_bits(c);
-  r[3] = (short)bf16_bits(d);
-  return r;
+typedef float v2f32 __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf16 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values to packed BF16 (round to nearest even; one v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  const v2f32 x = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, v2bf16));
 }
 
 __device__ __forceinline__ v4s16 load4(const uint16_t* p) {
@@ -58,73 +66,157 @@ __device__ __forceinline__ v4s16 load4(const uint16_t* p) {
   return r;
 }
 
-// Pre-activations of one 16-sample tile t of the 64 staged samples
-// (xs: LDS, BF16 bits [64][16]).  a1[mb][r] and a2[mb][r] are hidden unit
-// 16 mb + 4 (l/16) + r of sample 16 t + l%16.  Returns that sample's output
-// in every lane (after the fold, all four lane groups hold it).
-__device__ __forceinline__ float mlp_tile(const uint8_t* __restrict__ pk,
-                                          const uint16_t* xs, int t, int lane, v4f32* a1,
-                                          v4f32* a2) {
-  const uint16_t* w1 = reinterpret_cast<const uint16_t*>(pk + kPkW1);
-  const uint16_t* w2 = reinterpret_cast<const uint16_t*>(pk + kPkW2);
-  const float* b1 = reinterpret_cast<const float*>(pk + kPkB1);
-  const float* b2 = reinterpret_cast<const float*>(pk + kPkB2);
-  const float* w3 = reinterpret_cast<const float*>(pk + kPkW3);
-  const int row = lane & 15, quad = lane >> 4;
-  const v4s16 xb = load4(xs + (16 * t + row) * kMlpInPad + 4 * quad);
-  v4s16 h1[4];
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
-    const float4 bb = *reinterpret_cast<const float4*>(b1 + 16 * mb + 4 * quad);
-    v4f32 c = {bb.x, bb.y, bb.z, bb.w};
-    const v4s16 a = load4(w1 + (16 * mb + row) * kMlpInPad + 4 * quad);
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb, c, 0, 0, 0);
-    a1[mb] = c;
-    h1[mb] = pack4(fmaxf(c[0], 0.f), fmaxf(c[1], 0.f), fmaxf(c[2], 0.f), fmaxf(c[3], 0.f));
-  }
-  float s = 0.f;
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
-    const float4 bb = *reinterpret_cast<const float4*>(b2 + 16 * mb + 4 * quad);
-    v4f32 c = {bb.x, bb.y, bb.z, bb.w};
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      const v4s16 a = load4(w2 + (16 * mb + row) * kMlpH + 16 * kb + 4 * quad);
-      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[kb], c, 0, 0, 0);
-    }
-    a2[mb] = c;
-    const float4 ww = *reinterpret_cast<const float4*>(w3 + 16 * mb + 4 * quad);
-    s += ww.x * bf16_round(fmaxf(c[0], 0.f));
-    s += ww.y * bf16_round(fmaxf(c[1], 0.f));
-    s += ww.z * bf16_round(fmaxf(c[2], 0.f));
-    s += ww.w * bf16_round(fmaxf(c[3], 0.f));
-  }
-  s += __shfl_xor(s, 16);
-  s += __shfl_xor(s, 32);
-  return s + *reinterpret_cast<const float*>(pk + kPkB3);
+// Where the network's weights are read from: the packed image in global
+// memory (row strides 16 / 64) or a copy in LDS with padded rows.
+struct MlpView {
+  const uint16_t* w1;  // BF16 [64][w1s], 12 used columns + zeros
+  const uint16_t* w2;  // BF16 [64][w2s]
+  const float* b1;
+  const float* b2;
+  const uint16_t* w3;  // BF16 [64]
+  float b3;
+  int w1s, w2s;
+};
+
+__device__ __forceinline__ MlpView mlp_global(const uint8_t* pk) {
+  MlpView v;
+  v.w1 = reinterpret_cast<const uint16_t*>(pk + kPkW1);
+  v.w2 = reinterpret_cast<const uint16_t*>(pk + kPkW2);
+  v.b1 = reinterpret_cast<const float*>(pk + kPkB1);
+  v.b2 = reinterpret_cast<const float*>(pk + kPkB2);
+  v.w3 = reinterpret_cast<const uint16_t*>(pk + kPkW3);
+  v.b3 = *reinterpret_cast<const float*>(pk + kPkB3);
+  v.w1s = kMlpInPad;
+  v.w2s = kMlpH;
+  return v;
 }
 
-// Network output for the sample staged in LDS row `lane` (all 64 lanes must
-// be active; rows of lanes without a sample may hold anything finite).
-__device__ __forceinline__ float mlp_scores64(const uint8_t* __restrict__ pk, const uint16_t* xs,
-                                              int lane) {
+// LDS copy.  Row strides of 20 and 68 BF16 (40 and 136 bytes) put the 16
+// rows one 16-lane group reads at distinct even banks, so the 8-byte A
+// operand loads are conflict-free.
+constexpr int kW1Ld = 20, kW2Ld = 68, kXsLd = 20;
+struct MlpLds {
+  uint16_t w1[kMlpH * kW1Ld];
+  uint16_t w2[kMlpH * kW2Ld];
+  float b1[kMlpH], b2[kMlpH];
+  uint16_t w3[kMlpH];
+  float b3;
+};
+
+// Copies the packed image into L with nthr threads (thread index tid); the
+// caller synchronises before use.
+__device__ __forceinline__ void mlp_load_lds(MlpLds& L, const uint8_t* __restrict__ pk, int tid,
+                                             int nthr) {
+  const uint32_t* w1 = reinterpret_cast<const uint32_t*>(pk + kPkW1);
+  const uint32_t* w2 = reinterpret_cast<const uint32_t*>(pk + kPkW2);
+  for (int i = tid; i < kMlpH * kMlpInPad / 2; i += nthr) {
+    const int r = i / (kMlpInPad / 2), k = i % (kMlpInPad / 2);
+    reinterpret_cast<uint32_t*>(L.w1)[r * (kW1Ld / 2) + k] = w1[i];
+  }
+  for (int i = tid; i < kMlpH * kMlpH / 2; i += nthr) {
+    const int r = i / (kMlpH / 2), k = i % (kMlpH / 2);
+    reinterpret_cast<uint32_t*>(L.w2)[r * (kW2Ld / 2) + k] = w2[i];
+  }
+  for (int i = tid; i < kMlpH; i += nthr) {
+    L.b1[i] = reinterpret_cast<const float*>(pk + kPkB1)[i];
+    L.b2[i] = reinterpret_cast<const float*>(pk + kPkB2)[i];
+    L.w3[i] = reinterpret_cast<const uint16_t*>(pk + kPkW3)[i];
+  }
+  if (tid == 0) L.b3 = *reinterpret_cast<const float*>(pk + kPkB3);
+}
+
+__device__ __forceinline__ MlpView mlp_lds(const MlpLds& L) {
+  MlpView v;
+  v.w1 = L.w1;
+  v.w2 = L.w2;
+  v.b1 = L.b1;
+  v.b2 = L.b2;
+  v.w3 = L.w3;
+  v.b3 = L.b3;
+  v.w1s = kW1Ld;
+  v.w2s = kW2Ld;
+  return v;
+}
+
+// Pre-activations of one 16-sample tile t of the staged samples (xs: LDS,
+// BF16 rows of stride xss).  a1[mb][r] and a2[mb][r] are hidden unit
+// 16 mb + 4 (l/16) + r of sample 16 t + l%16.  Returns that sample's output
+// in every lane (after the fold, all four lane groups hold it).
+__device__ __forceinline__ float mlp_tile(const MlpView& V, const uint16_t* xs, int xss, int t,
+                                          int lane, v4f32* a1, v4f32* a2) {
+  const int row = lane & 15, quad = lane >> 4;
+  const v4s16 xb = load4(xs + (16 * t + row) * xss + 4 * quad);
+  uint2 h[4];  // BF16 pairs of the lane's 4 outputs per 16-row block
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const float4 bb = *reinterpret_cast<const float4*>(V.b1 + 16 * mb + 4 * quad);
+    v4f32 c = {bb.x, bb.y, bb.z, bb.w};
+    const v4s16 a = load4(V.w1 + (16 * mb + row) * V.w1s + 4 * quad);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb, c, 0, 0, 0);
+    a1[mb] = c;
+    h[mb].x = pk_bf16(fmaxf(c[0], 0.f), fmaxf(c[1], 0.f));
+    h[mb].y = pk_bf16(fmaxf(c[2], 0.f), fmaxf(c[3], 0.f));
+  }
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const float4 bb = *reinterpret_cast<const float4*>(V.b2 + 16 * mb + 4 * quad);
+    v4f32 c = {bb.x, bb.y, bb.z, bb.w};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint16_t* wr = V.w2 + (16 * mb + row) * V.w2s + 32 * q + 4 * quad;
+      const uint2 lo = *reinterpret_cast<const uint2*>(wr);
+      const uint2 hi = *reinterpret_cast<const uint2*>(wr + 16);
+      const v4u32 a = {lo.x, lo.y, hi.x, hi.y};
+      const v4u32 b = {h[2 * q].x, h[2 * q].y, h[2 * q + 1].x, h[2 * q + 1].y};
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16, a),
+                                                  __builtin_bit_cast(v8bf16, b), c, 0, 0, 0);
+    }
+    a2[mb] = c;
+  }
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    h[mb].x = pk_bf16(fmaxf(a2[mb][0], 0.f), fmaxf(a2[mb][1], 0.f));
+    h[mb].y = pk_bf16(fmaxf(a2[mb][2], 0.f), fmaxf(a2[mb][3], 0.f));
+  }
+  // Layer 3: every row of A is w3 (same K order as layer 2).
+  v4f32 y = {V.b3, V.b3, V.b3, V.b3};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const uint2 lo = *reinterpret_cast<const uint2*>(V.w3 + 32 * q + 4 * quad);
+    const uint2 hi = *reinterpret_cast<const uint2*>(V.w3 + 32 * q + 16 + 4 * quad);
+    const v4u32 a = {lo.x, lo.y, hi.x, hi.y};
+    const v4u32 b = {h[2 * q].x, h[2 * q].y, h[2 * q + 1].x, h[2 * q + 1].y};
+    y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16, a),
+                                                __builtin_bit_cast(v8bf16, b), y, 0, 0, 0);
+  }
+  return y[0];
+}
+
+// Network outputs of staged rows 0 .. 16 ntiles - 1: lane l receives row
+// l's.  All 64 lanes must be active; rows without a sample may hold any
+// bits (each output column depends on its own input column only).
+__device__ __forceinline__ float mlp_scores(const MlpView& V, const uint16_t* xs, int xss,
+                                            int lane, int ntiles) {
   float y = 0.f;
   v4f32 a1[4], a2[4];
 #pragma unroll 1
-  for (int t = 0; t < 4; ++t) {
-    const float s = mlp_tile(pk, xs, t, lane, a1, a2);
+  for (int t = 0; t < ntiles; ++t) {
+    // Re-read the weights for every tile (cheap from LDS) instead of letting
+    // the compiler keep ~90 VGPRs of them live across the caller's loop.
+    asm volatile("" ::: "memory");
+    const float s = mlp_tile(V, xs, xss, t, lane, a1, a2);
     if ((lane >> 4) == t) y = s;
   }
   return y;
 }
 
-// Stages one lane's 12 features as a BF16 row of 16 (4 zero columns).
-__device__ __forceinline__ void mlp_stage(uint16_t* xs, int lane, const float* f) {
-  uint32_t* row = reinterpret_cast<uint32_t*>(xs + lane * kMlpInPad);
+// Stages 12 features as BF16 row `row` (stride xss >= 16, 4 zero columns).
+__device__ __forceinline__ void mlp_stage(uint16_t* xs, int xss, int row, const float* f) {
+  uint32_t* r = reinterpret_cast<uint32_t*>(xs + row * xss);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) row[k] = bf16_bits(f[2 * k]) | (bf16_bits(f[2 * k + 1]) << 16);
-  row[6] = 0;
-  row[7] = 0;
+  for (int k = 0; k < 6; ++k) r[k] = bf16_bits(f[2 * k]) | (bf16_bits(f[2 * k + 1]) << 16);
+  r[6] = 0;
+  r[7] = 0;
 }
 
 }  // namespace dev

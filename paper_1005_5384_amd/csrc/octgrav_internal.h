@@ -50,8 +50,8 @@ constexpr int kPkW1 = 0;                              // BF16 [64][16]
 constexpr int kPkW2 = kPkW1 + kMlpH * kMlpInPad * 2;  // BF16 [64][64]
 constexpr int kPkB1 = kPkW2 + kMlpH * kMlpH * 2;      // FP32 [64]
 constexpr int kPkB2 = kPkB1 + kMlpH * 4;              // FP32 [64]
-constexpr int kPkW3 = kPkB2 + kMlpH * 4;              // FP32 [64], BF16-rounded values
-constexpr int kPkB3 = kPkW3 + kMlpH * 4;              // FP32
+constexpr int kPkW3 = kPkB2 + kMlpH * 4;              // BF16 [64]
+constexpr int kPkB3 = kPkW3 + kMlpH * 2;              // FP32
 constexpr int kPkBytes = kPkB3 + 256;
 
 // ------------------------------------------------------------------ device
@@ -61,7 +61,8 @@ struct DevTree {
   const int32_t* topo;   // int4 [nc]
   const float* geo;      // float4 [nc]  boundary; the side's sign bit marks leaves
   const float* wrec;     // float4 x2 [nc] walk record: boundary (as geo) | topo
-  const float* ext;      // float4 [nc] FP32 tight-box extents xyz, depth
+  const float* fcell;    // float4 x2 [nc] learned-criterion cell features: extents xyz,
+                         // log2(1+depth)/log2(22) | M, |Q|_F, |com - centre|, 0
   const int32_t* iperm;  // [n] caller index -> sorted position
   const float* mp;       // float4 x3 [nc]
   const int32_t* ginfo;  // int4 [ng]
@@ -81,6 +82,7 @@ struct WalkBufs {
   int64_t* blk;        // scan scratch: 2 per scan block
   int32_t* ovf_list;   // [max(ng, nw)] groups / work items whose LDS frontier overflowed
   int32_t* ovf_count;  // [1]
+  int32_t* wctr;       // [8 x 64]: per-XCD work counters (stride 64) of persistent kernels
   int32_t* gq;         // global frontier queues for the fallback walk
   int64_t gq_cap;      // entries per queue (power of two)
   int32_t gq_waves;    // queues (waves) of the fallback walk

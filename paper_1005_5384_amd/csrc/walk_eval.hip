@@ -156,8 +156,8 @@ template <bool PLAIN, bool LEARNED, typename SH, typename Q>
 __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64_t w,
                               float th2, float eps2, float* __restrict__ acc,
                               float* __restrict__ pot, Q q, uint32_t qmask, bool gmem_q,
-                              bool do_eval, int cw, int* nband_out) {
-  const int lane = threadIdx.x;
+                              bool do_eval, int cw, int* nband_out, const MlpView* mv) {
+  const int lane = threadIdx.x & (kLanes - 1);
   const int2 wk = reinterpret_cast<const int2*>(T.work)[w];
   const int64_t g = wk.x;
   const int4 gi = reinterpret_cast<const int4*>(T.ginfo)[g];
@@ -180,7 +180,8 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
   // learned criterion state
   const bool trace = LEARNED && B.tr_s != nullptr && wk.y == 0;
   const int64_t trb = trace ? B.tr_off[g] : 0, tre = trace ? B.tr_off[g + 1] : 0;
-  const float mtot = LEARNED ? reinterpret_cast<const float4*>(T.mp)[0].w : 0.f;
+  const MacGroup mg =
+      mac_group(gmin, gmax, LEARNED ? reinterpret_cast<const float4*>(T.mp)[0].w : 1.f);
   double sum2 = 0.0;
   int nband = 0;
   const int64_t xcb = exp ? B.c_off[g] : 0, xce = exp ? B.c_off[g + 1] : 0;
@@ -219,21 +220,23 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
       const uint64_t mB = __ballot(band);
       bool accb = false;
       if (mB) {
-        float f[kMlpIn];
-#pragma unroll
-        for (int k = 0; k < kMlpIn; ++k) f[k] = 0.f;
-        if (band) {
-          const float4* mp = reinterpret_cast<const float4*>(T.mp);
-          mac_features(gmin, gmax, ge, mp[3 * (int64_t)c], mp[3 * (int64_t)c + 1],
-                       mp[3 * (int64_t)c + 2], reinterpret_cast<const float4*>(T.ext)[c], mtot, f);
-        }
+        // Band lanes stage their features as consecutive rows; the network
+        // runs on ceil(rows / 16) tiles and each lane picks its row's output.
+        const int rk = rank_below(mB);
         uint16_t* xs = reinterpret_cast<uint16_t*>(sh.tile);
-        mlp_stage(xs, lane, f);
+        if (band) {
+          const float4* fc = reinterpret_cast<const float4*>(T.fcell);
+          float f[kMlpIn];
+          mac_features(mg, ge, fc[2 * (int64_t)c], fc[2 * (int64_t)c + 1], f);
+          mlp_stage(xs, kXsLd, rk, f);
+        }
         wave_lds_sync();
-        const float yh = mlp_scores64(B.mlp, xs, lane);
+        const float yrow = mlp_scores(*mv, xs, kXsLd, lane, (__popcll(mB) + 15) >> 4);
         wave_lds_sync();
+        const float yh = __shfl(yrow, rk);
         accb = band && yh <= B.mac_ltau;
-        if (accb) sum2 += exp10(2.0 * (double)yh);
+        // 10^(2 y) = 2^(2 log2(10) y) on the FP32 exp unit; summed in FP64
+        if (accb) sum2 += (double)__builtin_amdgcn_exp2f(yh * 6.64385618977472f);
         if (band && trace) {
           const int64_t k = trb + nband + rank_below(mB);
           if (k < tre) {
@@ -352,16 +355,16 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
 template <bool PLAIN, bool LEARNED, typename SH, typename Q>
 __device__ int walk_eval_one(const DevTree& T, const WalkBufs& B, SH& sh, int64_t w, float th2,
                              float eps2, float* acc, float* pot, Q q, uint32_t qmask, bool gmem_q,
-                             bool do_eval) {
+                             bool do_eval, const MlpView* mv) {
   int nb = 0;
   const int st = walk_eval_item<PLAIN, LEARNED>(T, B, sh, w, th2, eps2, acc, pot, q, qmask, gmem_q,
-                                                do_eval, 0, &nb);
+                                                do_eval, 0, &nb, mv);
   if (!LEARNED || st != kFallBack) return st;
   return walk_eval_item<PLAIN, false>(T, B, sh, w, th2, eps2, acc, pot, q, qmask, gmem_q, do_eval,
-                                      2 * nb + 1, &nb);
+                                      2 * nb + 1, &nb, mv);
 }
 
-template <bool PLAIN, int QCAP, bool LEARNED>
+template <bool PLAIN, int QCAP>
 __global__ __launch_bounds__(kLanes) void walk_eval_kernel(DevTree T, WalkBufs B, float th2,
                                                            float eps2, float* acc, float* pot,
                                                            int do_eval) {
@@ -369,10 +372,45 @@ __global__ __launch_bounds__(kLanes) void walk_eval_kernel(DevTree T, WalkBufs B
   const int64_t w = xcd_slab(blockIdx.x, gridDim.x, T.nw);
   if (w < 0) return;
   const uint32_t qmask = (uint32_t)min(B.lds_qcap, QCAP) - 1;
-  if (walk_eval_one<PLAIN, LEARNED>(T, B, sh, w, th2, eps2, acc, pot, sh.q, qmask, false,
-                                    do_eval != 0) == kOverflow &&
+  if (walk_eval_one<PLAIN, false>(T, B, sh, w, th2, eps2, acc, pot, sh.q, qmask, false,
+                                  do_eval != 0, nullptr) == kOverflow &&
       threadIdx.x == 0)
     B.ovf_list[atomicAdd(B.ovf_count, 1)] = (int32_t)w;
+}
+
+// Learned criterion: persistent blocks of kLWaves independent waves that
+// share one LDS copy of the network (loaded once per block).  Each XCD owns a
+// contiguous (Morton) range of work items, handed out one at a time through
+// a per-XCD counter (work items differ a lot in cost); a wave whose XCD's
+// range is exhausted helps the other XCDs.
+constexpr int kLWaves = 4;
+
+template <bool PLAIN, int QCAP>
+__global__ __launch_bounds__(kLWaves * kLanes) void walk_eval_learned_kernel(
+    DevTree T, WalkBufs B, float th2, float eps2, float* acc, float* pot, int do_eval) {
+  __shared__ WShared<QCAP> shw[kLWaves];
+  __shared__ MlpLds ml;
+  mlp_load_lds(ml, B.mlp, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const MlpView V = mlp_lds(ml);
+  const int wv = threadIdx.x / kLanes, lane = threadIdx.x & (kLanes - 1);
+  const int64_t per = (T.nw + 7) / 8;
+  const uint32_t qmask = (uint32_t)min(B.lds_qcap, QCAP) - 1;
+  for (int s = 0; s < 8; ++s) {
+    const int x = (blockIdx.x + s) & 7;
+    const int64_t lo = x * per, n = max((int64_t)0, min(per, T.nw - lo));
+    for (;;) {
+      int k = 0;
+      if (lane == 0) k = atomicAdd(B.wctr + 64 * x, 1);
+      k = __shfl(k, 0);
+      if (k >= n) break;
+      const int64_t w = lo + k;
+      if (walk_eval_one<PLAIN, true>(T, B, shw[wv], w, th2, eps2, acc, pot, shw[wv].q, qmask,
+                                     false, do_eval != 0, &V) == kOverflow &&
+          lane == 0)
+        B.ovf_list[atomicAdd(B.ovf_count, 1)] = (int32_t)w;
+    }
+  }
 }
 
 // Global-memory queues: written and read by different lanes of one wave, so
@@ -388,11 +426,19 @@ __global__ __launch_bounds__(kLanes) void walk_eval_fallback_kernel(DevTree T, W
                                                                     float* acc, float* pot,
                                                                     int do_eval) {
   __shared__ WShared<64> sh;
+  __shared__ std::conditional_t<LEARNED, MlpLds, char> ml;
+  MlpView V{};
+  if constexpr (LEARNED) {
+    if (*B.ovf_count == 0) return;
+    mlp_load_lds(ml, B.mlp, threadIdx.x, blockDim.x);
+    __syncthreads();
+    V = mlp_lds(ml);
+  }
   const int n = *B.ovf_count;
   GQueue q{B.gq + (int64_t)blockIdx.x * B.gq_cap};
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const int st = walk_eval_one<PLAIN, LEARNED>(T, B, sh, B.ovf_list[i], th2, eps2, acc, pot, q,
-                                                 (uint32_t)(B.gq_cap - 1), true, do_eval != 0);
+                                                 (uint32_t)(B.gq_cap - 1), true, do_eval != 0, &V);
     if (st == kOverflow && threadIdx.x == 0)
       atomicOr(reinterpret_cast<unsigned long long*>(&B.tot[5]), 1ull);
   }
@@ -400,6 +446,7 @@ __global__ __launch_bounds__(kLanes) void walk_eval_fallback_kernel(DevTree T, W
 
 __global__ void fused_init_kernel(WalkBufs B) {
   if (threadIdx.x < 8) B.tot[threadIdx.x] = 0;
+  if (threadIdx.x < 8) B.wctr[64 * threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     *B.ovf_count = 0;
     B.c_off[0] = 0;  // base of an offsets scan of the counts this walk writes
@@ -419,13 +466,19 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
   // which grows like theta^-3: 1024 entries cover theta >= 0.45 on Plummer
   // spheres of 2^20 (peak ~740 at 0.5), 4096 the smaller angles.  Work items
   // that still overflow go to the fallback kernel.
-  // The learned walk opens no more than the theta_lo walk does.
   const bool learned = B.mlp != nullptr;
-  const bool wide = theta < 0.45f || learned;
+  const bool wide = theta < 0.45f;
   auto go = [&](auto plain_tag, auto learned_tag) {
     constexpr bool P = decltype(plain_tag)::value, L = decltype(learned_tag)::value;
-    if (wide) walk_eval_kernel<P, 4096, L><<<grid, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
-    else walk_eval_kernel<P, 1024, L><<<grid, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
+    if constexpr (L) {
+      // 3 blocks of 4 waves fit a CU's LDS (4 x 9 KB frontiers + 12 KB network)
+      walk_eval_learned_kernel<P, 1024><<<8 * 96, kLWaves * kLanes, 0, s>>>(T, B, th2, eps2, acc,
+                                                                           pot, do_eval);
+    } else if (wide) {
+      walk_eval_kernel<P, 4096><<<grid, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
+    } else {
+      walk_eval_kernel<P, 1024><<<grid, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
+    }
     walk_eval_fallback_kernel<P, L><<<B.gq_waves, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
   };
   if (learned) {

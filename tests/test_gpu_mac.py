@@ -57,7 +57,8 @@ def test_band_features_labels_match_oracle(plummer, stride):
     assert gid.size == rg.size > 0
     assert np.array_equal(gid, rg) and np.array_equal(cid, rc)
     rf = R.mac_features(rg, rc)
-    np.testing.assert_allclose(feat, rf, rtol=2e-6, atol=2e-6)
+    # hardware reciprocal, square root and log2 on the GPU (about 1 ulp each)
+    np.testing.assert_allclose(feat, rf, rtol=1e-5, atol=1e-6)
     rad, _ = oracle.direct(pos, m, eps)
     rl = R.mac_labels(rad, eps, rg, rc)
     big = rl >= 1e-6
