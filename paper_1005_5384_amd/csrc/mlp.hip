@@ -109,41 +109,58 @@ __device__ __forceinline__ void kahan(float& s, float& c, float v) {
   s = t;
 }
 
-// One thread per parameter (plus one for the mean loss): sums over the batch.
+// Gradient sums over the batch, split over kSplit slices of the batch
+// (blockIdx.y): one thread per parameter (plus one for the loss) per slice
+// writes a compensated partial sum; mlp_grad_reduce_kernel adds the slices.
+constexpr int kSplit = 32;
+
 __global__ __launch_bounds__(256) void mlp_grad_kernel(
     const float* __restrict__ x, const float* __restrict__ a1s, const float* __restrict__ a2s,
     const float* __restrict__ dh1s, const float* __restrict__ dh2s, const float* __restrict__ dys,
-    const float* __restrict__ losss, int64_t B, float* __restrict__ grad, double* loss) {
+    const float* __restrict__ losss, int64_t B, float* __restrict__ part) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > kMlpParams) return;
+  const int64_t b0 = B * blockIdx.y / kSplit, b1 = B * (blockIdx.y + 1) / kSplit;
+  float s = 0.f, c = 0.f;
+  if (p == kMlpParams) {
+    for (int64_t b = b0; b < b1; ++b) kahan(s, c, losss[b]);
+  } else if (p < kOffB1) {
+    const int j = p / kMlpIn, k = p % kMlpIn;
+    for (int64_t b = b0; b < b1; ++b)
+      kahan(s, c, bf16_round(dh1s[b * kMlpH + j]) * bf16_round(x[b * kMlpIn + k]));
+  } else if (p < kOffW2) {
+    const int j = p - kOffB1;
+    for (int64_t b = b0; b < b1; ++b) kahan(s, c, dh1s[b * kMlpH + j]);
+  } else if (p < kOffB2) {
+    const int q = p - kOffW2, j = q / kMlpH, k = q % kMlpH;
+    for (int64_t b = b0; b < b1; ++b)
+      kahan(s, c, bf16_round(dh2s[b * kMlpH + j]) * bf16_round(fmaxf(a1s[b * kMlpH + k], 0.f)));
+  } else if (p < kOffW3) {
+    const int j = p - kOffB2;
+    for (int64_t b = b0; b < b1; ++b) kahan(s, c, dh2s[b * kMlpH + j]);
+  } else if (p < kOffB3) {
+    const int k = p - kOffW3;
+    for (int64_t b = b0; b < b1; ++b) kahan(s, c, dys[b] * bf16_round(fmaxf(a2s[b * kMlpH + k], 0.f)));
+  } else {
+    for (int64_t b = b0; b < b1; ++b) kahan(s, c, dys[b]);
+  }
+  part[(int64_t)blockIdx.y * (kMlpParams + 1) + p] = s - c;
+}
+
+__global__ __launch_bounds__(256) void mlp_grad_reduce_kernel(const float* __restrict__ part,
+                                                              int64_t B, float* __restrict__ grad,
+                                                              double* loss) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > kMlpParams) return;
   if (p == kMlpParams) {
     double s = 0.0;
-    for (int64_t b = 0; b < B; ++b) s += (double)losss[b];
+    for (int k = 0; k < kSplit; ++k) s += (double)part[(int64_t)k * (kMlpParams + 1) + p];
     *loss = s / (double)B;
     return;
   }
   float s = 0.f, c = 0.f;
-  if (p < kOffB1) {
-    const int j = p / kMlpIn, k = p % kMlpIn;
-    for (int64_t b = 0; b < B; ++b)
-      kahan(s, c, bf16_round(dh1s[b * kMlpH + j]) * bf16_round(x[b * kMlpIn + k]));
-  } else if (p < kOffW2) {
-    const int j = p - kOffB1;
-    for (int64_t b = 0; b < B; ++b) kahan(s, c, dh1s[b * kMlpH + j]);
-  } else if (p < kOffB2) {
-    const int q = p - kOffW2, j = q / kMlpH, k = q % kMlpH;
-    for (int64_t b = 0; b < B; ++b)
-      kahan(s, c, bf16_round(dh2s[b * kMlpH + j]) * bf16_round(fmaxf(a1s[b * kMlpH + k], 0.f)));
-  } else if (p < kOffW3) {
-    const int j = p - kOffB2;
-    for (int64_t b = 0; b < B; ++b) kahan(s, c, dh2s[b * kMlpH + j]);
-  } else if (p < kOffB3) {
-    const int k = p - kOffW3;
-    for (int64_t b = 0; b < B; ++b) kahan(s, c, dys[b] * bf16_round(fmaxf(a2s[b * kMlpH + k], 0.f)));
-  } else {
-    for (int64_t b = 0; b < B; ++b) kahan(s, c, dys[b]);
-  }
-  grad[p] = s;
+  for (int k = 0; k < kSplit; ++k) kahan(s, c, part[(int64_t)k * (kMlpParams + 1) + p]);
+  grad[p] = s - c;
 }
 
 __global__ void mlp_adam_kernel(float* __restrict__ P, float* __restrict__ m, float* __restrict__ v,
@@ -174,15 +191,18 @@ int launch_mlp_forward(const void* pk, const float* x, int64_t B, float* y, floa
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+int64_t mlp_grad_scratch_floats() { return (int64_t)kSplit * (kMlpParams + 1); }
+
 int launch_mlp_loss_grad(const void* pk, const float* x, const float* tgt, int64_t B, float tau,
                          float* y, float* a1s, float* a2s, float* dh1s, float* dh2s, float* dys,
-                         float* losss, float* grad, double* loss, void* stream) {
+                         float* losss, float* part, float* grad, double* loss, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   if (launch_mlp_forward(pk, x, B, y, a1s, a2s, stream)) return -1;
   mlp_backward_kernel<<<(B + 255) / 256, 256, 0, s>>>((const uint8_t*)pk, a1s, a2s, y, tgt, B, tau,
                                                       dh1s, dh2s, dys, losss);
-  mlp_grad_kernel<<<(kMlpParams + 1 + 255) / 256, 256, 0, s>>>(x, a1s, a2s, dh1s, dh2s, dys, losss,
-                                                               B, grad, loss);
+  const int nb = (kMlpParams + 1 + 255) / 256;
+  mlp_grad_kernel<<<dim3(nb, kSplit), 256, 0, s>>>(x, a1s, a2s, dh1s, dh2s, dys, losss, B, part);
+  mlp_grad_reduce_kernel<<<nb, 256, 0, s>>>(part, B, grad, loss);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
