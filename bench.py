@@ -65,7 +65,7 @@ def cpu_baseline(pos, m, w, gpu_acc, gpu_pot, n_groups_sample=1024):
     }
 
 
-def learned_vs_theta(T, w, steps, band=(0.3, 1.0), beta=8.0, target=1e-3):
+def learned_vs_theta(T, w, steps, band=(0.4, 0.8), beta=30.0, target=1e-3):
     """The learned acceptance criterion against the opening angle at equal
     p99 relative force error (against the GPU direct sum on the 4096-particle
     sample): theta* by bisection, then tau_pair (budget = beta * tau_pair) by

@@ -23,6 +23,8 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # keep IEEE FP32 denormals (the opening test is bit-exact against the host)
     "-fno-gpu-flush-denormals-to-zero",
+    # matrix-core results straight in VGPRs (no accumulation-register copies)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
 ]
 CXX_FLAGS = ["-std=c++17", "-O3", "-fopenmp", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",

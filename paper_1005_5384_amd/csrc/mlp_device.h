@@ -57,13 +57,17 @@ __device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
 }
 
 __device__ __forceinline__ v4s16 load4(const uint16_t* p) {
-  const uint2 u = *reinterpret_cast<const uint2*>(p);
-  v4s16 r;
-  r[0] = (short)(u.x & 0xFFFFu);
-  r[1] = (short)(u.x >> 16);
-  r[2] = (short)(u.y & 0xFFFFu);
-  r[3] = (short)(u.y >> 16);
-  return r;
+  return __builtin_bit_cast(v4s16, *reinterpret_cast<const uint2*>(p));
+}
+
+typedef short v2s16 __attribute__((ext_vector_type(2)));
+
+// ReLU of two packed BF16 values: as 16-bit integers, negative BF16 values
+// (and -0) are negative, so a signed max with 0 clears exactly them
+// (relu(bf16(x)) == bf16(relu(x))).  One v_pk_max_i16.
+__device__ __forceinline__ uint32_t relu_pk(uint32_t h) {
+  const v2s16 z = {0, 0};
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(v2s16, h), z));
 }
 
 // Where the network's weights are read from: the packed image in global
@@ -154,8 +158,8 @@ __device__ __forceinline__ float mlp_tile(const MlpView& V, const uint16_t* xs, 
     const v4s16 a = load4(V.w1 + (16 * mb + row) * V.w1s + 4 * quad);
     c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb, c, 0, 0, 0);
     a1[mb] = c;
-    h[mb].x = pk_bf16(fmaxf(c[0], 0.f), fmaxf(c[1], 0.f));
-    h[mb].y = pk_bf16(fmaxf(c[2], 0.f), fmaxf(c[3], 0.f));
+    h[mb].x = relu_pk(pk_bf16(c[0], c[1]));
+    h[mb].y = relu_pk(pk_bf16(c[2], c[3]));
   }
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
@@ -175,8 +179,8 @@ __device__ __forceinline__ float mlp_tile(const MlpView& V, const uint16_t* xs, 
   }
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
-    h[mb].x = pk_bf16(fmaxf(a2[mb][0], 0.f), fmaxf(a2[mb][1], 0.f));
-    h[mb].y = pk_bf16(fmaxf(a2[mb][2], 0.f), fmaxf(a2[mb][3], 0.f));
+    h[mb].x = relu_pk(pk_bf16(a2[mb][0], a2[mb][1]));
+    h[mb].y = relu_pk(pk_bf16(a2[mb][2], a2[mb][3]));
   }
   // Layer 3: every row of A is w3 (same K order as layer 2).
   v4f32 y = {V.b3, V.b3, V.b3, V.b3};
@@ -212,11 +216,10 @@ __device__ __forceinline__ float mlp_scores(const MlpView& V, const uint16_t* xs
 
 // Stages 12 features as BF16 row `row` (stride xss >= 16, 4 zero columns).
 __device__ __forceinline__ void mlp_stage(uint16_t* xs, int xss, int row, const float* f) {
-  uint32_t* r = reinterpret_cast<uint32_t*>(xs + row * xss);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) r[k] = bf16_bits(f[2 * k]) | (bf16_bits(f[2 * k + 1]) << 16);
-  r[6] = 0;
-  r[7] = 0;
+  uint4* r = reinterpret_cast<uint4*>(xs + row * xss);
+  r[0] = make_uint4(pk_bf16(f[0], f[1]), pk_bf16(f[2], f[3]), pk_bf16(f[4], f[5]),
+                    pk_bf16(f[6], f[7]));
+  r[1] = make_uint4(pk_bf16(f[8], f[9]), pk_bf16(f[10], f[11]), 0u, 0u);
 }
 
 }  // namespace dev
