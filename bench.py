@@ -24,45 +24,65 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (spec sheet)
 FLOP_PP, FLOP_PC = 38, 70  # the paper's per-interaction convention (Sec. 3.3)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_eval_kernel_plummer1m_theta0.5_traffic.md")
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the default kernel from the committed counter
+    summary, if the kernel's sources are still the ones it was taken with."""
+    import hashlib
+    import re
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+        d = json.loads(re.search(r"```json\n(.*?)```", txt, re.S).group(1))
+        h = hashlib.sha256()
+        for f in d["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        return d["traffic_bytes"] if h.hexdigest() == d["source_sha256"] else None
+    except (OSError, AttributeError, KeyError, ValueError):
+        return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pos, m, w, gpu_acc, gpu_pot, n_groups_sample=1024):
-    """The oracle as it stands, on a bounded sample of the same workload:
-    its own tree build plus the same-tree walk and FP64 evaluation of a
-    seeded sample of groups, and the FP64 direct sum for 4096 sampled
+def cpu_baseline(pos, m, w, gpu_acc, gpu_pot):
+    """The oracle as it stands on the same workload: its own tree build, the
+    same-tree walk and FP64 evaluation of every group at theta = 0.5 (the
+    whole force call), and the FP64 direct sum for the 4096 sampled
     particles (the tree-error reference)."""
     import oracle
     cores = oracle.num_threads()
     t0 = time.perf_counter()
     O = oracle.Tree(pos, m, w["n_leaf"], 64)
     t_build = time.perf_counter() - t0
-    rng = np.random.default_rng(4096)
-    sel = np.sort(rng.choice(O.n_groups, min(n_groups_sample, O.n_groups), replace=False))
     t0 = time.perf_counter()
-    ar, pr = O.forces(0.5, w["eps"], groups=sel)
+    ar, pr = O.forces(0.5, w["eps"])
     t_eval = time.perf_counter() - t0
-    k = ~np.isnan(pr)
-    n_sample = int(k.sum())
-    ea = oracle.rel_err(gpu_acc[k], ar[k])
-    ep = oracle.rel_err(gpu_pot[k], pr[k])
-    tg = np.sort(rng.choice(pos.shape[0], 4096, replace=False))
+    n = pos.shape[0]
+    ea = oracle.rel_err(gpu_acc, ar)
+    ep = oracle.rel_err(gpu_pot, pr)
+    tg = W_sample(pos.shape[0], w)
     t0 = time.perf_counter()
     ad, _ = oracle.direct(pos, m, w["eps"], targets=tg)
     t_direct = time.perf_counter() - t0
-    e_dir = oracle.rel_err(gpu_acc[tg], ad)
     return {
-        "value": n_sample / t_eval, "unit": "particles/s", "cores": cores, "kind": "oracle",
-        "sample": (f"same-tree FP64 walk+evaluation of {len(sel)} seeded groups "
-                   f"({n_sample} particles) of the 2^20 Plummer tree at theta=0.5; "
-                   f"oracle tree build {t_build:.2f} s; FP64 direct sum of 4096 sampled "
-                   f"particles {t_direct:.2f} s"),
+        "value": n / t_eval, "unit": "particles/s", "cores": cores, "kind": "oracle",
+        "sample": (f"the whole 2^20 Plummer force call at theta=0.5 (same-tree FP64 walk + "
+                   f"evaluation of all {O.n_groups} groups, {t_eval:.2f} s); oracle tree build "
+                   f"{t_build:.2f} s; FP64 direct sum of the {len(tg)} sampled particles "
+                   f"{t_direct:.2f} s"),
         "eval_s": t_eval,
         "gpu_vs_same_tree_oracle": {"acc_med": float(np.median(ea)), "acc_max": float(ea.max()),
                                     "pot_med": float(np.median(ep)), "pot_max": float(ep.max())},
-        "gpu_vs_direct_fp64": oracle.err_summary(gpu_acc[tg], ad) | {"n": 4096},
+        "gpu_vs_direct_fp64": oracle.err_summary(gpu_acc[tg], ad) | {"n": len(tg)},
     }
+
+
+def W_sample(n, w):
+    from paper_1005_5384_amd import workloads as W
+    return W.sample_indices(n, w.get("sample", 4096), w.get("sample_seed", 4096))
 
 
 def learned_vs_theta(T, w, steps, band=(0.4, 0.8), beta=30.0, target=1e-3):
@@ -137,6 +157,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-criterion vs theta comparison at equal p99 error")
+    ap.add_argument("--mac", default="theta", choices=["theta", "learned"],
+                    help="acceptance criterion of the timed steps")
+    ap.add_argument("--tau", type=float, default=3.57e-4,
+                    help="tau_pair of --mac learned (band 0.4-0.8, budget 30 tau)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the bench: time a plain device copy of this many bytes "
                          "(the reference for scaling hardware byte counters)")
@@ -177,6 +201,10 @@ def main():
     acc = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     pot = torch.empty(n, dtype=torch.float32, device="cuda")
     theta, eps = args.theta, w["eps"]
+    if args.mac == "learned":
+        from paper_1005_5384_amd import learned as L
+        net = og.Mlp(L.load_params())
+        T.set_mac(net, 0.4, 0.8, args.tau, 30.0 * args.tau)
 
     for _ in range(args.warmup):
         T.forces(theta, eps, acc=acc, pot=pot, timed=True, path=args.path)
@@ -214,14 +242,18 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "distribution": w["gen"], "theta": theta,
-                   "eps": eps, "n_leaf": w["n_leaf"], "n_group": 64, "mac": "theta",
+                   "eps": eps, "n_leaf": w["n_leaf"], "n_group": 64, "mac": args.mac,
                    "accumulation": "compensated",
                    "path": args.path or "default"},
         "roofline": {"bound": "alu",
-                     "kernel": "evaluation phase (walk included for fused paths)",
+                     "kernel": ("walk_eval_kernel: fused walk + evaluation, HIP-event phase on "
+                                "the library's stream (two-pass path: eval_kernel)"),
                      "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": (recorded_traffic() if (args.workload == "plummer1m" and theta == 0.5
+                                                        and args.path is None and args.mac == "theta")
+                                 else None),
                      "flops_per_launch": flops, "flop_convention": "38 per p-p, 70 per p-c"},
         "path_frac_peak": path_tflops / PEAK_FP32_TFLOPS,
         "path_tflops": path_tflops,
@@ -231,6 +263,11 @@ def main():
         "host_build_upload_s": t_build,
         "tree": T.stats,
     }
+    if args.mac == "learned":
+        out["config"].update({"tau_pair": args.tau, "theta_lo": 0.4, "theta_hi": 0.8,
+                              "budget": 30.0 * args.tau})
+        out["mac_stats"] = T.mac_stats()
+        T.set_mac(None)
     if not args.no_learned:
         log("bench: learned criterion vs theta at p99 1e-3 ...")
         out["learned_vs_theta"] = learned_vs_theta(T, w, args.steps)
