@@ -176,26 +176,29 @@ struct octgrav_tree {
       std::memcpy(&wrec[8 * c], &geo_dev[4 * c], 16);
       std::memcpy(&wrec[8 * c + 4], &h.topo[4 * c], 16);
     }
-    // The cell-only parts of the learned criterion's features, in FP32 from
-    // the FP32 images: tight-box extents, log2(1 + depth) / log2(22) | mass,
-    // Frobenius norm of Q, |com - boundary centre|.  And the inverse
-    // permutation for direct sums.
+    // The learned criterion's features that depend on the cell only, in FP32
+    // from the FP32 images with the feature definitions' own expressions:
+    // log10(M/M_tot)/3, |Q|_F/(M l^2), extents/l (3), log2(1 + depth)/log2(22),
+    // |com - boundary centre|/l.  And the inverse permutation for direct sums.
     std::vector<float> fcell((size_t)nc * 8);
+    const float mtot = h.mp[3];
     for (int64_t c = 0; c < nc; ++c) {
       float* o = &fcell[8 * c];
       const float* m = &h.mp[12 * c];
       const float* gc = &h.geo[4 * c];
-      for (int k = 0; k < 3; ++k) o[k] = (float)(h.box[6 * c + 3 + k] - h.box[6 * c + k]);
-      o[3] = std::log2(1.0f + (float)h.depth[c]) / std::log2(22.0f);
-      o[4] = m[3];
-      o[5] = std::sqrt((m[4] * m[4] + m[5] * m[5] + m[6] * m[6]) +
-                       2.0f * (m[7] * m[7] + m[8] * m[8] + m[9] * m[9]));
+      const float l = gc[3], M = m[3];
+      const float qn = std::sqrt((m[4] * m[4] + m[5] * m[5] + m[6] * m[6]) +
+                                 2.0f * (m[7] * m[7] + m[8] * m[8] + m[9] * m[9]));
       float s2 = 0.0f;
       for (int k = 0; k < 3; ++k) {
         const float d = m[k] - gc[k];
         s2 += d * d;
       }
-      o[6] = std::sqrt(s2);
+      o[0] = std::log10(M / mtot) / 3.0f;
+      o[1] = qn / (M * l * l);
+      for (int k = 0; k < 3; ++k) o[2 + k] = (float)(h.box[6 * c + 3 + k] - h.box[6 * c + k]) / l;
+      o[5] = std::log2(1.0f + (float)h.depth[c]) / std::log2(22.0f);
+      o[6] = std::sqrt(s2) / l;
       o[7] = 0.0f;
     }
     std::vector<int32_t> iperm(n);

@@ -112,19 +112,20 @@ struct Sum4 {
 };
 
 // The 12 input features of the learned acceptance criterion for candidate
-// cell c seen from a group's tight box, in FP32: d/l, log10(M/M_tot)/3,
-// |Q|_F/(M l^2), log2(1 + r_g/l), cell extents / l, log2(1 + group
-// extents / l), log2(1 + depth)/log2(22), |com - boundary centre| / l.
-// The group's part (MacGroup) is computed once per group and the cell's
-// part (fc0 = extents, depth term; fc1 = M, |Q|_F, |com - centre|) once per
-// cell on the host; the rest uses the hardware reciprocal, square root and
-// log2 (about 1 ulp each: the features are rounded to BF16 for the network).
+// cell c seen from a group's tight box, in FP32: f0 = d/l, f1 =
+// log10(M/M_tot)/3, f2 = |Q|_F/(M l^2), f3 = log2(1 + r_g/l), f4..6 = cell
+// extents / l, f7..9 = log2(1 + group extents / l), f10 = log2(1 +
+// depth)/log2(22), f11 = |com - boundary centre| / l.  The cell-only ones
+// (f1, f2, f4..6, f10, f11) come precomputed per cell (fc0, fc1); the group's
+// part (MacGroup) is computed once per group; f0, f3 and f7..9 use the
+// hardware reciprocal, square root and log2 (about 1 ulp each: the features
+// are rounded to BF16 for the network).
 struct MacGroup {
   float4 gmin, gmax;
-  float gx, gy, gz, rg, rmtot;
+  float gx, gy, gz, rg;
 };
 
-__device__ __forceinline__ MacGroup mac_group(float4 gmin, float4 gmax, float mtot) {
+__device__ __forceinline__ MacGroup mac_group(float4 gmin, float4 gmax) {
 #pragma clang fp contract(off)
   MacGroup G;
   G.gmin = gmin;
@@ -133,31 +134,28 @@ __device__ __forceinline__ MacGroup mac_group(float4 gmin, float4 gmax, float mt
   G.gy = gmax.y - gmin.y;
   G.gz = gmax.z - gmin.z;
   G.rg = 0.5f * __builtin_amdgcn_sqrtf((G.gx * G.gx + G.gy * G.gy) + G.gz * G.gz);
-  G.rmtot = __builtin_amdgcn_rcpf(mtot);
   return G;
 }
 
 __device__ __forceinline__ void mac_features(const MacGroup& G, float4 geo, float4 fc0,
                                              float4 fc1, float* f) {
 #pragma clang fp contract(off)
-  const float l = fabsf(geo.w), rl = __builtin_amdgcn_rcpf(l);
+  const float rl = __builtin_amdgcn_rcpf(fabsf(geo.w));
   const float tx = fmaxf(fmaxf(G.gmin.x - geo.x, geo.x - G.gmax.x), 0.0f);
   const float ty = fmaxf(fmaxf(G.gmin.y - geo.y, geo.y - G.gmax.y), 0.0f);
   const float tz = fmaxf(fmaxf(G.gmin.z - geo.z, geo.z - G.gmax.z), 0.0f);
-  const float d = __builtin_amdgcn_sqrtf((tx * tx + ty * ty) + tz * tz);
-  constexpr float kLog10_2_over_3 = 0.100343331887994f;  // log10(2) / 3
-  f[0] = d * rl;
-  f[1] = __builtin_amdgcn_logf(fc1.x * G.rmtot) * kLog10_2_over_3;
-  f[2] = fc1.y * __builtin_amdgcn_rcpf(fc1.x * l * l);
+  f[0] = __builtin_amdgcn_sqrtf((tx * tx + ty * ty) + tz * tz) * rl;
+  f[1] = fc0.x;
+  f[2] = fc0.y;
   f[3] = __builtin_amdgcn_logf(1.0f + G.rg * rl);
-  f[4] = fc0.x * rl;
-  f[5] = fc0.y * rl;
-  f[6] = fc0.z * rl;
+  f[4] = fc0.z;
+  f[5] = fc0.w;
+  f[6] = fc1.x;
   f[7] = __builtin_amdgcn_logf(1.0f + G.gx * rl);
   f[8] = __builtin_amdgcn_logf(1.0f + G.gy * rl);
   f[9] = __builtin_amdgcn_logf(1.0f + G.gz * rl);
-  f[10] = fc0.w;
-  f[11] = fc1.z * rl;
+  f[10] = fc1.y;
+  f[11] = fc1.z;
 }
 
 // Every S-th entry of an LDS tile, starting at `first`, two at a time so the

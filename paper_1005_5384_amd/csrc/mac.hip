@@ -128,10 +128,9 @@ __global__ __launch_bounds__(kThreads) void mac_label_kernel(DevTree T, WalkBufs
     const float4* gbox = reinterpret_cast<const float4*>(T.gbox);
     const float4 geo = reinterpret_cast<const float4*>(T.geo)[c];
     const float4* fc = reinterpret_cast<const float4*>(T.fcell);
-    const float mtot = mp[0].w;  // the root cell's mass (cell 0, first float4: com, M)
     if (gout) gout[p] = (int32_t)g;
     if (cout) cout[p] = c;
-    mac_features(mac_group(gbox[2 * g], gbox[2 * g + 1], mtot), geo, fc[2 * (int64_t)c],
+    mac_features(mac_group(gbox[2 * g], gbox[2 * g + 1]), geo, fc[2 * (int64_t)c],
                  fc[2 * (int64_t)c + 1], feat + 12 * p);
   }
 }

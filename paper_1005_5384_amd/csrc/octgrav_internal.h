@@ -61,8 +61,8 @@ struct DevTree {
   const int32_t* topo;   // int4 [nc]
   const float* geo;      // float4 [nc]  boundary; the side's sign bit marks leaves
   const float* wrec;     // float4 x2 [nc] walk record: boundary (as geo) | topo
-  const float* fcell;    // float4 x2 [nc] learned-criterion cell features: extents xyz,
-                         // log2(1+depth)/log2(22) | M, |Q|_F, |com - centre|, 0
+  const float* fcell;    // float4 x2 [nc] learned-criterion features of the cell alone:
+                         // f1, f2, f4, f5 | f6, f10, f11, 0 (see mac_features)
   const int32_t* iperm;  // [n] caller index -> sorted position
   const float* mp;       // float4 x3 [nc]
   const int32_t* ginfo;  // int4 [ng]

@@ -182,8 +182,7 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
   // learned criterion state
   const bool trace = LEARNED && B.tr_s != nullptr && wk.y == 0;
   const int64_t trb = trace ? B.tr_off[g] : 0, tre = trace ? B.tr_off[g + 1] : 0;
-  const MacGroup mg =
-      mac_group(gmin, gmax, LEARNED ? reinterpret_cast<const float4*>(T.mp)[0].w : 1.f);
+  const MacGroup mg = mac_group(gmin, gmax);
   double sum2 = 0.0;
   int nband = 0;
   const int64_t xcb = exp ? B.c_off[g] : 0, xce = exp ? B.c_off[g + 1] : 0;
@@ -210,10 +209,16 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
     int c = 0;
     float4 ge = make_float4(0.f, 0.f, 0.f, 0.f);
     int4 tp = make_int4(0, 0, 0, 0);
+    float4 fc0 = make_float4(0.f, 0.f, 0.f, 0.f), fc1 = fc0;
     if (valid) {
       c = (int)q[(head + lane) & qmask];
       ge = rec[2 * (int64_t)c];
       tp = reinterpret_cast<const int4*>(rec)[2 * (int64_t)c + 1];
+      if (LEARNED) {  // issued with the walk record: one gather latency per step, not two
+        const float4* fc = reinterpret_cast<const float4*>(T.fcell);
+        fc0 = fc[2 * (int64_t)c];
+        fc1 = fc[2 * (int64_t)c + 1];
+      }
     }
     bool op;
     if (LEARNED) {
@@ -227,9 +232,8 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
         const int rk = rank_below(mB);
         uint16_t* xs = reinterpret_cast<uint16_t*>(sh.tile);
         if (band) {
-          const float4* fc = reinterpret_cast<const float4*>(T.fcell);
           float f[kMlpIn];
-          mac_features(mg, ge, fc[2 * (int64_t)c], fc[2 * (int64_t)c + 1], f);
+          mac_features(mg, ge, fc0, fc1, f);
           mlp_stage(xs, kXsLd, rk, f);
         }
         wave_lds_sync();
@@ -380,17 +384,15 @@ __global__ __launch_bounds__(kLanes) void walk_eval_kernel(DevTree T, WalkBufs B
     B.ovf_list[atomicAdd(B.ovf_count, 1)] = (int32_t)w;
 }
 
-// Persistent blocks of kLWaves independent waves (with the learned
+// Persistent blocks of NW independent waves (with the learned
 // criterion they share one LDS copy of the network, loaded once per block).
 // Each XCD owns a contiguous (Morton) range of work items, handed out one at
 // a time through a per-XCD counter (work items differ a lot in cost); a wave
 // whose XCD's range is exhausted helps the other XCDs.
-constexpr int kLWaves = 4;
-
-template <bool PLAIN, int QCAP, bool LEARNED>
-__global__ __launch_bounds__(kLWaves * kLanes) void walk_eval_persistent_kernel(
+template <bool PLAIN, int QCAP, bool LEARNED, int NW>
+__global__ __launch_bounds__(NW * kLanes) void walk_eval_persistent_kernel(
     DevTree T, WalkBufs B, float th2, float eps2, float* acc, float* pot, int do_eval) {
-  __shared__ WShared<QCAP> shw[kLWaves];
+  __shared__ WShared<QCAP> shw[NW];
   __shared__ std::conditional_t<LEARNED, MlpLds, char> ml;
   MlpView V{};
   if constexpr (LEARNED) {
@@ -477,13 +479,13 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
     constexpr bool P = decltype(plain_tag)::value, L = decltype(learned_tag)::value;
     if constexpr (L) {
       // 3 blocks of 4 waves fit a CU's LDS (4 x 9 KB frontiers + 12 KB network)
-      walk_eval_persistent_kernel<P, 1024, true><<<8 * 96, kLWaves * kLanes, 0, s>>>(
+      walk_eval_persistent_kernel<P, 1024, true, 4><<<8 * 96, 4 * kLanes, 0, s>>>(
           T, B, th2, eps2, acc, pot, do_eval);
     } else if (wide) {
       walk_eval_kernel<P, 4096><<<grid, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
     } else {
       // 4 blocks of 4 waves (4 x 9 KB frontiers) per CU
-      walk_eval_persistent_kernel<P, 1024, false><<<8 * 128, kLWaves * kLanes, 0, s>>>(
+      walk_eval_persistent_kernel<P, 1024, false, 4><<<8 * 128, 4 * kLanes, 0, s>>>(
           T, B, th2, eps2, acc, pot, do_eval);
     }
     walk_eval_fallback_kernel<P, L><<<B.gq_waves, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
