@@ -225,7 +225,11 @@ struct octgrav_tree {
     wb.ovf_list = (int32_t*)p;
     if ((rc = dalloc(&p, 4))) return rc;
     wb.ovf_count = (int32_t*)p;
-    if ((rc = dalloc(&p, 8 * 64 * 4))) return rc;
+    if ((rc = dalloc(&p, (size_t)std::max(ng, nw) * 4))) return rc;
+    wb.ovf_list2 = (int32_t*)p;
+    if ((rc = dalloc(&p, 4))) return rc;
+    wb.ovf_count2 = (int32_t*)p;
+    if ((rc = dalloc(&p, 9 * 64 * 4))) return rc;
     wb.wctr = (int32_t*)p;
     // Fallback frontier queues: a breadth-first FIFO never holds more than
     // two consecutive levels, hence at most twice the widest level.

@@ -82,7 +82,10 @@ struct WalkBufs {
   int64_t* blk;        // scan scratch: 2 per scan block
   int32_t* ovf_list;   // [max(ng, nw)] groups / work items whose LDS frontier overflowed
   int32_t* ovf_count;  // [1]
-  int32_t* wctr;       // [8 x 64]: per-XCD work counters (stride 64) of persistent kernels
+  int32_t* ovf_list2;  // [max(ng, nw)] second-tier overflows (fused wave kernels)
+  int32_t* ovf_count2; // [1]
+  int32_t* wctr;       // [9 x 64]: work counters (stride 64) of persistent kernels:
+                       // 8 per-XCD ranges, 1 overflow list
   int32_t* gq;         // global frontier queues for the fallback walk
   int64_t gq_cap;      // entries per queue (power of two)
   int32_t gq_waves;    // queues (waves) of the fallback walk

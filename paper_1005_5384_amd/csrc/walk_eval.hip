@@ -370,30 +370,28 @@ __device__ int walk_eval_one(const DevTree& T, const WalkBufs& B, SH& sh, int64_
                                       2 * nb + 1, &nb, mv);
 }
 
-template <bool PLAIN, int QCAP>
-__global__ __launch_bounds__(kLanes) void walk_eval_kernel(DevTree T, WalkBufs B, float th2,
-                                                           float eps2, float* acc, float* pot,
-                                                           int do_eval) {
-  __shared__ WShared<QCAP> sh;
-  const int64_t w = xcd_slab(blockIdx.x, gridDim.x, T.nw);
-  if (w < 0) return;
-  const uint32_t qmask = (uint32_t)min(B.lds_qcap, QCAP) - 1;
-  if (walk_eval_one<PLAIN, false>(T, B, sh, w, th2, eps2, acc, pot, sh.q, qmask, false,
-                                  do_eval != 0, nullptr) == kOverflow &&
-      threadIdx.x == 0)
-    B.ovf_list[atomicAdd(B.ovf_count, 1)] = (int32_t)w;
+// Next work index from a shared counter, one atomic per wave.
+__device__ __forceinline__ int take_work(int32_t* ctr, int lane) {
+  int k = 0;
+  if (lane == 0) k = atomicAdd(ctr, 1);
+  return __shfl(k, 0);
 }
 
-// Persistent blocks of NW independent waves (with the learned
-// criterion they share one LDS copy of the network, loaded once per block).
-// Each XCD owns a contiguous (Morton) range of work items, handed out one at
-// a time through a per-XCD counter (work items differ a lot in cost); a wave
-// whose XCD's range is exhausted helps the other XCDs.
-template <bool PLAIN, int QCAP, bool LEARNED, int NW>
+// Persistent blocks of NW independent waves (with the learned criterion
+// they share one LDS copy of the network, loaded once per block).  Without
+// FROM_LIST each XCD owns a contiguous (Morton) range of work items, handed
+// out one at a time through a per-XCD counter (work items differ a lot in
+// cost), and a wave whose XCD's range is exhausted helps the other XCDs;
+// with FROM_LIST the items are the *src_n entries of src (the overflows of
+// an earlier tier), handed out through one counter.  Items whose frontier
+// outgrows this kernel's LDS queue are appended to (ovl, ovn).
+template <bool PLAIN, int QCAP, bool LEARNED, int NW, bool FROM_LIST>
 __global__ __launch_bounds__(NW * kLanes) void walk_eval_persistent_kernel(
-    DevTree T, WalkBufs B, float th2, float eps2, float* acc, float* pot, int do_eval) {
+    DevTree T, WalkBufs B, float th2, float eps2, float* acc, float* pot, int do_eval,
+    const int32_t* src, const int32_t* src_n, int32_t* ovl, int32_t* ovn) {
   __shared__ WShared<QCAP> shw[NW];
   __shared__ std::conditional_t<LEARNED, MlpLds, char> ml;
+  if (FROM_LIST && *src_n == 0) return;
   MlpView V{};
   if constexpr (LEARNED) {
     mlp_load_lds(ml, B.mlp, threadIdx.x, blockDim.x);
@@ -401,21 +399,31 @@ __global__ __launch_bounds__(NW * kLanes) void walk_eval_persistent_kernel(
     V = mlp_lds(ml);
   }
   const int wv = threadIdx.x / kLanes, lane = threadIdx.x & (kLanes - 1);
-  const int64_t per = (T.nw + 7) / 8;
   const uint32_t qmask = (uint32_t)min(B.lds_qcap, QCAP) - 1;
-  for (int s = 0; s < 8; ++s) {
-    const int x = (blockIdx.x + s) & 7;
-    const int64_t lo = x * per, n = max((int64_t)0, min(per, T.nw - lo));
+  if constexpr (FROM_LIST) {
     for (;;) {
-      int k = 0;
-      if (lane == 0) k = atomicAdd(B.wctr + 64 * x, 1);
-      k = __shfl(k, 0);
-      if (k >= n) break;
-      const int64_t w = lo + k;
+      const int k = take_work(B.wctr + 64 * 8, lane);
+      if (k >= *src_n) break;
+      const int32_t w = src[k];
       if (walk_eval_one<PLAIN, LEARNED>(T, B, shw[wv], w, th2, eps2, acc, pot, shw[wv].q, qmask,
                                         false, do_eval != 0, &V) == kOverflow &&
           lane == 0)
-        B.ovf_list[atomicAdd(B.ovf_count, 1)] = (int32_t)w;
+        ovl[atomicAdd(ovn, 1)] = w;
+    }
+  } else {
+    const int64_t per = (T.nw + 7) / 8;
+    for (int s = 0; s < 8; ++s) {
+      const int x = (blockIdx.x + s) & 7;
+      const int64_t lo = x * per, n = max((int64_t)0, min(per, T.nw - lo));
+      for (;;) {
+        const int k = take_work(B.wctr + 64 * x, lane);
+        if (k >= n) break;
+        const int64_t w = lo + k;
+        if (walk_eval_one<PLAIN, LEARNED>(T, B, shw[wv], w, th2, eps2, acc, pot, shw[wv].q,
+                                          qmask, false, do_eval != 0, &V) == kOverflow &&
+            lane == 0)
+          ovl[atomicAdd(ovn, 1)] = (int32_t)w;
+      }
     }
   }
 }
@@ -427,24 +435,28 @@ struct GQueue {
   __device__ volatile int32_t& operator[](uint32_t i) const { return p[i]; }
 };
 
+// Last tier: the *src_n items of src with global-memory frontier queues of
+// 2 x (widest tree level) entries, which a breadth-first FIFO cannot exceed.
 template <bool PLAIN, bool LEARNED>
 __global__ __launch_bounds__(kLanes) void walk_eval_fallback_kernel(DevTree T, WalkBufs B,
                                                                     float th2, float eps2,
                                                                     float* acc, float* pot,
-                                                                    int do_eval) {
+                                                                    int do_eval,
+                                                                    const int32_t* src,
+                                                                    const int32_t* src_n) {
   __shared__ WShared<64> sh;
   __shared__ std::conditional_t<LEARNED, MlpLds, char> ml;
+  const int n = *src_n;
+  if (n == 0) return;
   MlpView V{};
   if constexpr (LEARNED) {
-    if (*B.ovf_count == 0) return;
     mlp_load_lds(ml, B.mlp, threadIdx.x, blockDim.x);
     __syncthreads();
     V = mlp_lds(ml);
   }
-  const int n = *B.ovf_count;
   GQueue q{B.gq + (int64_t)blockIdx.x * B.gq_cap};
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const int st = walk_eval_one<PLAIN, LEARNED>(T, B, sh, B.ovf_list[i], th2, eps2, acc, pot, q,
+    const int st = walk_eval_one<PLAIN, LEARNED>(T, B, sh, src[i], th2, eps2, acc, pot, q,
                                                  (uint32_t)(B.gq_cap - 1), true, do_eval != 0, &V);
     if (st == kOverflow && threadIdx.x == 0)
       atomicOr(reinterpret_cast<unsigned long long*>(&B.tot[5]), 1ull);
@@ -453,9 +465,10 @@ __global__ __launch_bounds__(kLanes) void walk_eval_fallback_kernel(DevTree T, W
 
 __global__ void fused_init_kernel(WalkBufs B) {
   if (threadIdx.x < 8) B.tot[threadIdx.x] = 0;
-  if (threadIdx.x < 8) B.wctr[64 * threadIdx.x] = 0;
+  if (threadIdx.x < 9) B.wctr[64 * threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     *B.ovf_count = 0;
+    *B.ovf_count2 = 0;
     B.c_off[0] = 0;  // base of an offsets scan of the counts this walk writes
     B.l_off[0] = 0;
   }
@@ -467,28 +480,32 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
                      bool do_eval, float* acc, float* pot, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   const float th2 = theta * theta, eps2 = eps * eps;
-  const int64_t grid = ((T.nw + 7) / 8) * 8;
   fused_init_kernel<<<1, 64, 0, s>>>(B);
   // The breadth-first FIFO holds about two tree levels of the group's walk,
   // which grows like theta^-3: 1024 entries cover theta >= 0.45 on Plummer
-  // spheres of 2^20 (peak ~740 at 0.5), 4096 the smaller angles.  Work items
-  // that still overflow go to the fallback kernel.
+  // spheres of 2^20 (peak ~740 at 0.5), 4096 the smaller angles.  Tiers:
+  // 1024-entry LDS queues (theta >= 0.45 and the learned criterion; 16, or
+  // 12 with the network, waves per CU), then the overflows with 4096-entry
+  // LDS queues (one wave per block), then global-memory queues.
   const bool learned = B.mlp != nullptr;
-  const bool wide = theta < 0.45f;
+  const bool wide = theta < 0.45f && !learned;
   auto go = [&](auto plain_tag, auto learned_tag) {
     constexpr bool P = decltype(plain_tag)::value, L = decltype(learned_tag)::value;
-    if constexpr (L) {
-      // 3 blocks of 4 waves fit a CU's LDS (4 x 9 KB frontiers + 12 KB network)
-      walk_eval_persistent_kernel<P, 1024, true, 4><<<8 * 96, 4 * kLanes, 0, s>>>(
-          T, B, th2, eps2, acc, pot, do_eval);
-    } else if (wide) {
-      walk_eval_kernel<P, 4096><<<grid, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
+    if (wide) {
+      walk_eval_persistent_kernel<P, 4096, L, 1, false><<<8 * 224, kLanes, 0, s>>>(
+          T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list2, B.ovf_count2);
     } else {
-      // 4 blocks of 4 waves (4 x 9 KB frontiers) per CU
-      walk_eval_persistent_kernel<P, 1024, false, 4><<<8 * 128, 4 * kLanes, 0, s>>>(
-          T, B, th2, eps2, acc, pot, do_eval);
+      if constexpr (L)  // 3 blocks of 4 waves per CU (4 x 9 KB frontiers + 12 KB network)
+        walk_eval_persistent_kernel<P, 1024, L, 4, false><<<8 * 96, 4 * kLanes, 0, s>>>(
+            T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list, B.ovf_count);
+      else  // 4 blocks of 4 waves per CU
+        walk_eval_persistent_kernel<P, 1024, L, 4, false><<<8 * 128, 4 * kLanes, 0, s>>>(
+            T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list, B.ovf_count);
+      walk_eval_persistent_kernel<P, 4096, L, 1, true><<<8 * 64, kLanes, 0, s>>>(
+          T, B, th2, eps2, acc, pot, do_eval, B.ovf_list, B.ovf_count, B.ovf_list2, B.ovf_count2);
     }
-    walk_eval_fallback_kernel<P, L><<<B.gq_waves, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval);
+    walk_eval_fallback_kernel<P, L><<<B.gq_waves, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval,
+                                                                 B.ovf_list2, B.ovf_count2);
   };
   if (learned) {
     if (plain) go(std::true_type{}, std::true_type{});
