@@ -159,7 +159,7 @@ def main():
                     help="skip the learned-criterion vs theta comparison at equal p99 error")
     ap.add_argument("--mac", default="theta", choices=["theta", "learned"],
                     help="acceptance criterion of the timed steps")
-    ap.add_argument("--tau", type=float, default=3.57e-4,
+    ap.add_argument("--tau", type=float, default=4.21e-4,
                     help="tau_pair of --mac learned (band 0.4-0.8, budget 30 tau)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the bench: time a plain device copy of this many bytes "

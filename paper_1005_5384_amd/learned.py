@@ -54,7 +54,7 @@ def init_params(seed: int) -> np.ndarray:
     return P
 
 
-def train(x, y, epochs=40, batch=4096, lr=1e-3, tau=PINBALL_TAU, seed=0, params=None,
+def train(x, y, epochs=30, batch=4096, lr=1e-3, tau=PINBALL_TAU, seed=0, params=None,
           lr_final=1e-4, log=None):
     """Trains a network on (x, y) (CUDA tensors) with mini-batch Adam and a
     geometric learning-rate decay; returns the Mlp."""
@@ -130,7 +130,7 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     tr = sub.add_parser("train")
     tr.add_argument("--out", required=True)
-    tr.add_argument("--epochs", type=int, default=40)
+    tr.add_argument("--epochs", type=int, default=30)
     tr.add_argument("--stride", type=int, default=1)
     tr.add_argument("--seed", type=int, default=0)
     a = ap.parse_args()
