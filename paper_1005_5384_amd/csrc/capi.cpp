@@ -443,7 +443,7 @@ static Path choose_path(uint32_t flags, float theta) {
   if (flags & OCTGRAV_TWO_PASS) return Path::TwoPass;
   if (flags & OCTGRAV_FUSED_BLOCK) return Path::FusedBlock;
   if (flags & OCTGRAV_FUSED_WAVE) return Path::FusedWave;
-  return theta < 0.4f ? Path::FusedBlock : Path::FusedWave;
+  return theta < 0.45f ? Path::FusedBlock : Path::FusedWave;  // measured crossover
 }
 
 static int launch_fused(const octgrav_tree* t, Path p, float theta, float eps, bool plain,
