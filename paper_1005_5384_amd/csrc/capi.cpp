@@ -655,6 +655,8 @@ int octgrav_mac_collect(octgrav_tree* t, float theta_lo, float theta_hi, float e
     return fail(OCTGRAV_EINVAL, "bad collect arguments");
   try {
     // Band lists of every group (count walk, offsets, write walk in band mode).
+    // They replace the handle's lists: the counts of the last forces call are gone.
+    t->counts_valid = false;
     WalkBufs saved = t->wb;
     t->wb.band = 1;
     t->wb.band_hi2 = theta_hi * theta_hi;
@@ -691,9 +693,16 @@ int octgrav_mac_collect(octgrav_tree* t, float theta_lo, float theta_hi, float e
     *n_out = np;
     if (np == 0) return OCTGRAV_OK;
     void *dg = nullptr, *doff = nullptr;
-    if ((rc = t->dalloc(&dg, gs.size() * 4)) || (rc = t->dalloc(&doff, off.size() * 8))) return rc;
-    hipMemcpy(dg, gs.data(), gs.size() * 4, hipMemcpyHostToDevice);
-    hipMemcpy(doff, off.data(), off.size() * 8, hipMemcpyHostToDevice);
+    if ((rc = t->dalloc(&dg, gs.size() * 4)) || (rc = t->dalloc(&doff, off.size() * 8))) {
+      t->dfree(dg);
+      return rc;
+    }
+    if (hipMemcpy(dg, gs.data(), gs.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(doff, off.data(), off.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      t->dfree(dg);
+      t->dfree(doff);
+      return fail(OCTGRAV_EHIP, "sample upload failed");
+    }
     rc = launch_mac_labels(t->dt, t->wb, (const int32_t*)dg, (int64_t)gs.size(), (const int64_t*)doff,
                            acc_direct, eps, feat, label, group_out, cell_out, np, t->stream);
     if (!rc && hipStreamSynchronize(t->stream) != hipSuccess) rc = -1;
@@ -794,7 +803,12 @@ int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells
       t->dfree(d_c);
       return rc;
     }
-    hipMemcpy(d_off, off, (ng + 1) * 8, hipMemcpyHostToDevice);
+    if (hipMemcpy(d_off, off, (ng + 1) * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      t->dfree(d_off);
+      t->dfree(d_c);
+      t->dfree(d_s);
+      return fail(OCTGRAV_EHIP, "trace offsets upload failed");
+    }
     WalkBufs saved = t->wb;
     t->wb.tr_off = (const int64_t*)d_off;
     t->wb.tr_c = (int32_t*)d_c;

@@ -159,3 +159,28 @@ def test_allocation_failure_is_reported():
                        timeout=120)
     assert r.returncode == 0, r.stderr
     assert r.stdout.startswith("NULL") and "injected" in r.stdout
+
+
+def test_device_entry_points_reject_host_only_trees():
+    # Every entry point that needs the device copy refuses a host-only tree
+    # with OCTGRAV_EINVAL before touching the GPU.
+    import ctypes as C
+    pos, m = W.plummer(512, 3)
+    T = og.Tree(pos, m, 16, 64, host_only=True)
+    L = og.lib()
+    n = C.c_int64()
+    off = np.zeros(T.stats["n_groups"] + 1, np.int64)
+    fb = np.zeros(T.stats["n_groups"], np.int32)
+    assert L.octgrav_set_mac(T._h, None, 0.3, 1.0, 1e-3, 1.0) == og.EINVAL
+    assert L.octgrav_mac_trace(T._h, 0.5, og._ptr(off), None, None, 0, C.byref(n),
+                               og._ptr(fb)) == og.EINVAL
+    out = np.zeros(2, np.int64)
+    assert L.octgrav_mac_stats(T._h, og._ptr(out)) == og.EINVAL
+    assert L.octgrav_direct(T._h, 0.01, None, 0, None, None) == og.EINVAL
+    assert L.octgrav_mac_collect(T._h, 0.3, 1.0, 0.01, None, 1, None, None, None, None, 0,
+                                 C.byref(n)) == og.EINVAL
+    for rc in (L.octgrav_set_mac(None, None, 0.3, 1.0, 1e-3, 1.0),
+               L.octgrav_mlp_forward(None, None, 0, None),
+               L.octgrav_mlp_adam(None, 1e-3, 0.9, 0.999, 1e-8, 1)):
+        assert rc == og.EINVAL
+    assert og.last_error()
