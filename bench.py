@@ -47,7 +47,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pos, m, w, gpu_acc, gpu_pot):
+def cpu_baseline(pos, m, w, gpu_acc, gpu_pot, plain=None):
     """The oracle as it stands on the same workload: its own tree build, the
     same-tree walk and FP64 evaluation of every group at theta = 0.5 (the
     whole force call), and the FP64 direct sum for the 4096 sampled
@@ -76,8 +76,17 @@ def cpu_baseline(pos, m, w, gpu_acc, gpu_pot):
         "eval_s": t_eval,
         "gpu_vs_same_tree_oracle": {"acc_med": float(np.median(ea)), "acc_max": float(ea.max()),
                                     "pot_med": float(np.median(ep)), "pot_max": float(ep.max())},
+        **({} if plain is None else {"gpu_plain_sum_vs_same_tree_oracle": _errs(plain, ar, pr)}),
         "gpu_vs_direct_fp64": oracle.err_summary(gpu_acc[tg], ad) | {"n": len(tg)},
     }
+
+
+def _errs(out, ar, pr):
+    import oracle
+    ea = oracle.rel_err(out[0], ar)
+    ep = oracle.rel_err(out[1], pr)
+    return {"acc_med": float(np.median(ea)), "acc_max": float(ea.max()),
+            "pot_med": float(np.median(ep)), "pot_max": float(ep.max())}
 
 
 def W_sample(n, w):
@@ -271,11 +280,24 @@ def main():
     if not args.no_learned:
         log("bench: learned criterion vs theta at p99 1e-3 ...")
         out["learned_vs_theta"] = learned_vs_theta(T, w, args.steps)
+    # FP32 plain accumulation (no compensation) on the same call, for comparison
+    plain = None
+    if args.mac == "theta":
+        pa = torch.empty_like(acc)
+        pp = torch.empty_like(pot)
+        T.forces(theta, eps, acc=pa, pot=pp, plain=True, path=args.path)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            T.forces(theta, eps, acc=pa, pot=pp, plain=True, path=args.path)
+        torch.cuda.synchronize()
+        out["plain_sum_ms_per_step"] = (time.perf_counter() - t0) / args.steps * 1e3
+        plain = (pa.double().cpu().numpy(), pp.double().cpu().numpy())
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle) ...")
         a = acc.double().cpu().numpy()
         p = pot.double().cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(pos, m, w, a, p)
+        out["cpu_baseline"] = cpu_baseline(pos, m, w, a, p, plain)
         log("bench: cpu baseline done")
     print(json.dumps(out), flush=True)
 
