@@ -21,16 +21,17 @@
 // tile; plain FP32 per tile is folded into Neumaier pairs; slices are
 // combined in slice order.
 //
-// A work item whose frontier outgrows the LDS queue aborts before writing any
-// result and is redone by a fallback kernel whose queues live in global
-// memory, sized so that they cannot overflow.
+// A work item whose frontier outgrows its LDS queue aborts before writing any
+// result and is redone by the next tier: 1024-entry LDS queues, then
+// 4096-entry LDS queues, then queues in global memory sized so that they
+// cannot overflow.
 //
 // Learned acceptance criterion (LEARNED): candidates the test at theta_lo
 // accepts are accepted, those the test at theta_hi opens are opened, and for
 // the band in between the wave computes the 12 features of its band lanes,
-// stages them in LDS and runs the network on the matrix cores (64 candidates
-// per step); a candidate is accepted iff the predicted log10 error is at most
-// log10 tau_pair.  The accepted band candidates' predicted errors add up
+// stages them as consecutive rows in LDS and runs the network on the matrix
+// cores over ceil(rows / 16) tiles; a candidate is accepted iff the predicted
+// log10 error is at most log10 tau_pair.  The accepted band candidates' predicted errors add up
 // (FP64, sqrt of the sum of squares) into the group's budget; a work item
 // whose group exceeds it drops its accumulators and walks again with the
 // call's theta.  Every work item of a group makes the same decisions (same
