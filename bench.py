@@ -27,18 +27,27 @@ FLOP_PP, FLOP_PC = 38, 70  # the paper's per-interaction convention (Sec. 3.3)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_eval_kernel_plummer1m_theta0.5_traffic.md")
 
 
+def source_digest(files):
+    """SHA-256 of the given sources with comments and blank lines removed (so
+    that only code changes invalidate a recorded measurement)."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in files:
+        txt = open(os.path.join(ROOT, f)).read()
+        txt = re.sub(r"//[^\n]*", "", txt) if not f.endswith(".py") else re.sub(r"#[^\n]*", "", txt)
+        h.update("\n".join(l.rstrip() for l in txt.splitlines() if l.strip()).encode())
+    return h.hexdigest()
+
+
 def recorded_traffic():
     """HBM bytes per launch of the default kernel from the committed counter
-    summary, if the kernel's sources are still the ones it was taken with."""
-    import hashlib
+    summary, if the kernel's code is still the one it was taken with."""
     import re
     try:
         txt = open(TRAFFIC_PROFILE).read()
         d = json.loads(re.search(r"```json\n(.*?)```", txt, re.S).group(1))
-        h = hashlib.sha256()
-        for f in d["sources"]:
-            h.update(open(os.path.join(ROOT, f), "rb").read())
-        return d["traffic_bytes"] if h.hexdigest() == d["source_sha256"] else None
+        return d["traffic_bytes"] if source_digest(d["sources"]) == d["source_sha256"] else None
     except (OSError, AttributeError, KeyError, ValueError):
         return None
 
