@@ -43,6 +43,9 @@ extern "C" {
 /* octgrav_build_tree_ex flags */
 #define OCTGRAV_BUILD_HOST_ONLY 1u /* build and keep the host tree only: no device
                                       memory, no HIP call; forces/lists return EINVAL */
+#define OCTGRAV_BUILD_DEVICE 2u    /* build the tree on the GPU (same tree, bit for bit, as
+                                      the host build); the host keeps only what the calls
+                                      need, the first octgrav_export_tree copies the rest */
 
 /* octgrav_forces_ex flags */
 #define OCTGRAV_PLAIN_SUM 1u /* plain FP32 accumulation instead of compensated */

@@ -96,7 +96,7 @@ struct octgrav_mlp {
   }
 };
 
-struct octgrav_tree {
+struct octgrav_tree : DevAlloc {
   HostTree h;
   bool dev = false;
   hipStream_t stream = nullptr;
@@ -127,6 +127,32 @@ struct octgrav_tree {
     for (hipEvent_t e : bev)
       if (e) hipEventDestroy(e);
     if (eval_stream) hipStreamDestroy(eval_stream);
+  }
+
+  int alloc(void** p, size_t bytes) override { return dalloc(p, bytes); }
+
+  // Device-built trees keep the FP64 boxes and moments, the boundary image,
+  // the particle order and the FP32 moments on the device until an export
+  // asks for them.
+  DeviceArrays darr;
+  bool host_partial = false;
+
+  int fetch_host_arrays() {
+    if (!host_partial) return OCTGRAV_OK;
+    const int64_t n = h.n, nc = h.n_cells();
+    h.perm.resize(n);
+    h.geo.resize((size_t)nc * 4);
+    h.mp.resize((size_t)nc * 12);
+    h.mp64.resize((size_t)nc * 10);
+    h.box.resize((size_t)nc * 6);
+    if (hipMemcpy(h.perm.data(), dt.perm, (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(h.geo.data(), darr.geo_host, (size_t)nc * 16, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(h.mp.data(), dt.mp, (size_t)nc * 48, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(h.mp64.data(), darr.mp64, (size_t)nc * 80, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(h.box.data(), darr.box, (size_t)nc * 48, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(OCTGRAV_EHIP, "tree copy-back failed");
+    host_partial = false;
+    return OCTGRAV_OK;
   }
 
   int dalloc(void** p, size_t bytes) {
@@ -210,6 +236,14 @@ struct octgrav_tree {
         (rc = upload(h.mp, &dt.mp)) || (rc = upload(h.ginfo, &dt.ginfo)) ||
         (rc = upload(h.gbox, &dt.gbox)) || (rc = upload(h.work, &dt.work)))
       return rc;
+    return alloc_walk_buffers();
+  }
+
+  // Walk and list buffers, scratch, events and the evaluation stream (after
+  // the tree arrays are on the device, from either build).
+  int alloc_walk_buffers() {
+    const int64_t n = h.n, ng = h.n_groups(), nw = (int64_t)h.work.size() / 2;
+    int rc;
     void* p;
     if ((rc = dalloc(&p, (size_t)ng * 16))) return rc;
     wb.cnt = (int32_t*)p;
@@ -358,8 +392,34 @@ octgrav_tree* octgrav_build_tree_ex(const float* pos, const float* mass, int64_t
                                     int32_t n_group, uint32_t flags) {
   g_err.clear();
   try {
-    octgrav_tree* t = new octgrav_tree;
     std::string err;
+    if ((flags & OCTGRAV_BUILD_DEVICE) && (flags & OCTGRAV_BUILD_HOST_ONLY)) {
+      fail(OCTGRAV_EINVAL, "OCTGRAV_BUILD_DEVICE and OCTGRAV_BUILD_HOST_ONLY exclude each other");
+      return nullptr;
+    }
+    if (flags & OCTGRAV_BUILD_DEVICE) {
+      if (!validate_inputs(pos, mass, n, n_leaf, n_group, err)) {
+        fail(OCTGRAV_EINVAL, err);
+        return nullptr;
+      }
+      octgrav_tree* t = new octgrav_tree;
+      if (build_device_tree(pos, mass, n, n_leaf, n_group, t->h, t->dt, t->darr, *t, t->stream,
+                            err) != 0) {
+        std::string keep = g_err.empty() ? err : g_err;
+        delete t;
+        fail(OCTGRAV_EHIP, keep);
+        return nullptr;
+      }
+      t->host_partial = true;
+      if (t->alloc_walk_buffers() != OCTGRAV_OK) {
+        std::string keep = g_err;
+        delete t;
+        g_err = keep;
+        return nullptr;
+      }
+      return t;
+    }
+    octgrav_tree* t = new octgrav_tree;
     if (!build_host_tree(pos, mass, n, n_leaf, n_group, t->h, err)) {
       delete t;
       fail(OCTGRAV_EINVAL, err);
@@ -413,6 +473,8 @@ int octgrav_tree_stats(const octgrav_tree* t, octgrav_stats* s) {
 
 int octgrav_export_tree(const octgrav_tree* t, const octgrav_tree_view* v) {
   if (!t || !v) return fail(OCTGRAV_EINVAL, "NULL argument");
+  // A device-built tree copies its arrays back on the first export.
+  if (int rc = const_cast<octgrav_tree*>(t)->fetch_host_arrays()) return rc;
   const HostTree& h = t->h;
   auto cp = [](auto* dst, const auto& src) {
     if (dst) std::memcpy(dst, src.data(), src.size() * sizeof(src[0]));
@@ -435,10 +497,11 @@ int octgrav_export_tree(const octgrav_tree* t, const octgrav_tree_view* v) {
 enum class Path { TwoPass, FusedBlock, FusedWave };
 
 // Path of a call: an explicit flag, else the fastest measured for theta on
-// 2^20 Plummer spheres (ms at theta 0.3 / 0.5 / 0.75: fused wave 16.0 / 3.10 /
-// 1.23, fused block 10.9 / 3.27 / 1.72, two-pass 11.9 / 3.44 / 1.55).  The
-// wave variant's 4096-entry LDS queue for small angles limits it to a few
-// walks per CU, where the block variant shares one queue among four waves.
+// 2^20 Plummer spheres (ms at theta 0.3 / 0.4 / 0.45 / 0.5 / 0.75: fused wave
+// 13.8 / 6.7 / 3.6 / 2.6 / 1.03, fused block 11.0 / 5.4 / 4.0 / 3.1 / 1.6,
+// two-pass 12.0 / 5.6 / 4.4 / 3.3 / 1.5).  The wave variant's 4096-entry LDS
+// queues for small angles limit it to a few walks per CU, where the block
+// variant shares one queue among four waves.
 static Path choose_path(uint32_t flags, float theta) {
   if (flags & OCTGRAV_TWO_PASS) return Path::TwoPass;
   if (flags & OCTGRAV_FUSED_BLOCK) return Path::FusedBlock;

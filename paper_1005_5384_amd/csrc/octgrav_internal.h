@@ -36,6 +36,10 @@ struct HostTree {
 // Builds the host tree; returns false with a message on bad input.
 bool build_host_tree(const float* pos, const float* mass, int64_t n, int n_leaf, int n_group,
                      HostTree& out, std::string& err);
+// Pieces shared by the host and device builds.
+bool validate_inputs(const float* pos, const float* mass, int64_t n, int n_leaf, int n_group,
+                     std::string& err);
+void root_cube(const double lo[3], const double hi[3], double corner[3], double* side);
 
 // ------------------------------------------------------------------ network
 // Learned acceptance criterion: 12 -> 64 -> 64 -> 1 with ReLU.
@@ -149,6 +153,25 @@ int launch_mlp_loss_grad(const void* pk, const float* x, const float* tgt, int64
 int64_t mlp_grad_scratch_floats();  // partial gradient sums of launch_mlp_loss_grad
 int launch_mlp_adam(float* P, float* m, float* v, const float* g, float lr, float b1, float b2,
                     float eps, float c1, float c2, void* stream);
+// Device tree build (same result as build_host_tree, computed on the GPU).
+// The persistent arrays are allocated through DevAlloc (owned by the
+// caller); DeviceArrays receives the FP64 boxes / moments, the unsigned
+// boundary image and the depths, which stay on the device.  Fills h with the
+// scalars and the small host arrays (depth, topo, groups, work).
+struct DevAlloc {
+  virtual int alloc(void** p, size_t bytes) = 0;
+  virtual ~DevAlloc() = default;
+};
+struct DeviceArrays {
+  const double* box = nullptr;     // [nc * 6]
+  const double* mp64 = nullptr;    // [nc * 10]
+  const float* geo_host = nullptr; // [nc * 4]
+  const int32_t* depth = nullptr;  // [nc]
+};
+int build_device_tree(const float* pos_h, const float* mass_h, int64_t n, int n_leaf, int n_group,
+                      HostTree& h, DevTree& dt, DeviceArrays& out, DevAlloc& alloc, void* stream,
+                      std::string& err);
+
 int launch_diag(const DevTree& T, const float* acc, const float* pot, double* part_sums,
                 double* out4, void* stream);
 int64_t scan_scratch_entries(int64_t ng);

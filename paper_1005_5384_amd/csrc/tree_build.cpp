@@ -94,8 +94,8 @@ void radix_sort(std::vector<uint64_t>& key, std::vector<int32_t>& idx) {
 
 }  // namespace
 
-bool build_host_tree(const float* pos, const float* mass, int64_t n, int n_leaf, int n_group,
-                     HostTree& T, std::string& err) {
+bool validate_inputs(const float* pos, const float* mass, int64_t n, int n_leaf, int n_group,
+                     std::string& err) {
   if (!pos || !mass) return err = "pos and mass must be non-NULL", false;
   if (n < 1 || n >= (int64_t(1) << 31)) return err = "n must satisfy 1 <= n < 2^31", false;
   if (n_leaf < 1 || n_leaf > 64) return err = "n_leaf must be in 1..64", false;
@@ -112,15 +112,10 @@ bool build_host_tree(const float* pos, const float* mass, int64_t n, int n_leaf,
   }
   if (bad_pos) return err = "positions must be finite with |x| < 2^60", false;
   if (bad_mass) return err = "masses must be finite and > 0", false;
+  return true;
+}
 
-  T = HostTree();
-  T.n = n;
-  T.n_leaf = n_leaf;
-  T.n_group = n_group;
-
-  // Root cube: centred on the bounding box, side the power of two S with
-  // ext < S <= 2 ext (S = 1 for a single point).
-  double lo[3], hi[3];
+void bounding_box(const float* pos, int64_t n, double lo[3], double hi[3]) {
   for (int k = 0; k < 3; ++k) {
     double a = pos[k], b = pos[k];
 #pragma omp parallel for reduction(min : a) reduction(max : b)
@@ -131,11 +126,29 @@ bool build_host_tree(const float* pos, const float* mass, int64_t n, int n_leaf,
     lo[k] = a;
     hi[k] = b;
   }
+}
+
+// Root cube: centred on the bounding box, side the power of two S with
+// ext < S <= 2 ext (S = 1 for a single point).
+void root_cube(const double lo[3], const double hi[3], double corner[3], double* side) {
   double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
   int e = 1;
   if (ext > 0) std::frexp(ext, &e);
-  T.side = ext > 0 ? std::ldexp(1.0, e) : 1.0;
-  for (int k = 0; k < 3; ++k) T.corner[k] = (lo[k] + hi[k]) * 0.5 - 0.5 * T.side;
+  *side = ext > 0 ? std::ldexp(1.0, e) : 1.0;
+  for (int k = 0; k < 3; ++k) corner[k] = (lo[k] + hi[k]) * 0.5 - 0.5 * *side;
+}
+
+bool build_host_tree(const float* pos, const float* mass, int64_t n, int n_leaf, int n_group,
+                     HostTree& T, std::string& err) {
+  if (!validate_inputs(pos, mass, n, n_leaf, n_group, err)) return false;
+  T = HostTree();
+  T.n = n;
+  T.n_leaf = n_leaf;
+  T.n_group = n_group;
+
+  double lo[3], hi[3];
+  bounding_box(pos, n, lo, hi);
+  root_cube(lo, hi, T.corner, &T.side);
 
   // Morton keys and the sort.
   const double step = std::ldexp(T.side, -kMaxDepth), inv = std::ldexp(1.0 / T.side, kMaxDepth);

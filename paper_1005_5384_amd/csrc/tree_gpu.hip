@@ -1,0 +1,580 @@
+// Octree construction on the GPU (the host build of Sec. 2.1 moved to the
+// device), bit-identical to the host build: the same 63-bit Morton keys from
+// the same FP64 grid arithmetic, a stable radix sort (ties by input index),
+// the same level-synchronous breadth-first subdivision, and FP64 boxes and
+// moments bottom-up with the host's operation order (no contraction, the
+// host's min / max), so every exported array matches bitwise.
+//
+// Per level: one thread per cell finds its octant boundaries by binary search
+// in the sorted keys and counts non-empty children; a scan numbers the
+// children; a second pass writes them.  Boxes and moments: one thread per
+// cell, deepest level first.  Then the FP32 images, the walk records, the
+// learned criterion's cell features, the groups (scattered to their first
+// particle and compacted, which orders them by first particle) and the work
+// chunks.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "octgrav_internal.h"
+
+namespace octgrav {
+namespace {
+
+constexpr uint32_t kGridMax = (1u << kMaxDepth) - 1;
+constexpr int kT = 256;
+
+inline int blocks(int64_t n) { return (int)((n + kT - 1) / kT); }
+
+// Bounding box: per-block min / max of each coordinate (FP32 values are
+// exact in FP64, so the order of the reduction does not matter).
+__global__ void bbox_kernel(const float* __restrict__ pos, int64_t n, float* __restrict__ part) {
+  __shared__ float sh[6][kT];
+  // min / max with the host's tie rule (keeps the earlier of equal values,
+  // so +0 / -0 resolve as they do on the host)
+  float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    for (int k = 0; k < 3; ++k) {
+      const float x = pos[3 * i + k];
+      v[k] = x < v[k] ? x : v[k];
+      v[3 + k] = v[3 + k] < x ? x : v[3 + k];
+    }
+  for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int k = 0; k < 6; ++k) {
+        const float a = sh[k][threadIdx.x], b = sh[k][threadIdx.x + o];
+        sh[k][threadIdx.x] = k < 3 ? (b < a ? b : a) : (a < b ? b : a);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// The host's grid coordinate: floor, then exact against the grid planes.
+__device__ __forceinline__ uint32_t grid_coord(double x, double corner, double step,
+                                               double inv_step) {
+#pragma clang fp contract(off)
+  const double f = floor((x - corner) * inv_step);
+  int64_t u = f < 0 ? 0 : (f > (double)kGridMax ? (int64_t)kGridMax : (int64_t)f);
+  while (u > 0 && corner + (double)u * step > x) --u;
+  while (u < (int64_t)kGridMax && corner + (double)(u + 1) * step <= x) ++u;
+  return (uint32_t)u;
+}
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffff;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+
+__global__ void keys_kernel(const float* __restrict__ pos, int64_t n, double cx, double cy,
+                            double cz, double step, double inv, uint64_t* __restrict__ key,
+                            int32_t* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t u0 = grid_coord((double)pos[3 * i], cx, step, inv);
+  const uint32_t u1 = grid_coord((double)pos[3 * i + 1], cy, step, inv);
+  const uint32_t u2 = grid_coord((double)pos[3 * i + 2], cz, step, inv);
+  key[i] = spread3(u0) | spread3(u1) << 1 | spread3(u2) << 2;
+  idx[i] = (int32_t)i;
+}
+
+struct Cells {
+  int32_t* first;   // first particle
+  int32_t* n;       // particles
+  int32_t* depth;
+  int32_t* parent;
+  int32_t* fc;      // first child (-1)
+  int32_t* nc;      // children
+};
+
+// Octant boundaries of the level's cells [lbeg, lbeg + m) at digit shift sh;
+// bd[9 j ..] and the count of non-empty children of cell lbeg + j.
+__global__ void split_kernel(Cells C, const uint64_t* __restrict__ key, int64_t lbeg, int64_t m,
+                             int L, int n_leaf, int32_t* __restrict__ bd,
+                             int32_t* __restrict__ nkid) {
+  const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (j >= m) return;
+  const int64_t c = lbeg + j;
+  const int32_t a = C.first[c], b = a + C.n[c];
+  if (C.n[c] <= n_leaf || L == kMaxDepth) {
+    nkid[j] = 0;
+    return;
+  }
+  const int sh = 3 * (kMaxDepth - 1 - L);
+  int32_t* d9 = bd + 9 * j;
+  d9[0] = a;
+  int32_t lo = a;
+  int cnt = 0;
+  for (int d = 1; d < 8; ++d) {
+    // first index in [lo, b) whose digit is >= d (digits are sorted)
+    int32_t l = lo, h = b;
+    while (l < h) {
+      const int32_t mid = l + ((h - l) >> 1);
+      if ((int)((key[mid] >> sh) & 7) < d) l = mid + 1;
+      else h = mid;
+    }
+    d9[d] = l;
+    cnt += l > lo;
+    lo = l;
+  }
+  d9[8] = b;
+  cnt += b > lo;
+  nkid[j] = cnt;
+}
+
+__global__ void emit_kernel(Cells C, int64_t lbeg, int64_t lend, int64_t m, int L,
+                            const int32_t* __restrict__ bd, const int32_t* __restrict__ nkid,
+                            const int32_t* __restrict__ pre) {
+  const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (j >= m || nkid[j] == 0) return;
+  const int64_t c = lbeg + j;
+  int64_t ch = lend + pre[j];
+  C.fc[c] = (int32_t)ch;
+  C.nc[c] = nkid[j];
+  const int32_t* d9 = bd + 9 * j;
+  for (int d = 0; d < 8; ++d)
+    if (d9[d + 1] > d9[d]) {
+      C.first[ch] = d9[d];
+      C.n[ch] = d9[d + 1] - d9[d];
+      C.depth[ch] = L + 1;
+      C.parent[ch] = (int32_t)c;
+      C.fc[ch] = -1;
+      C.nc[ch] = 0;
+      ++ch;
+    }
+}
+
+__global__ void gather_kernel(const float* __restrict__ pos, const float* __restrict__ mass,
+                              const int32_t* __restrict__ perm, int64_t n,
+                              float4* __restrict__ part, int32_t* __restrict__ iperm) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const int32_t p = perm[i];
+  part[i] = make_float4(pos[3 * p], pos[3 * p + 1], pos[3 * p + 2], mass[p]);
+  iperm[p] = (int32_t)i;
+}
+
+// The host's std::min / std::max on doubles.
+__device__ __forceinline__ double hmin(double a, double b) { return b < a ? b : a; }
+__device__ __forceinline__ double hmax(double a, double b) { return a < b ? b : a; }
+
+// Boxes and FP64 moments of the cells [a, b) (one level), as the host does.
+__global__ void moments_kernel(Cells C, const float4* __restrict__ part, int64_t a, int64_t b,
+                               double* __restrict__ box, double* __restrict__ mp64) {
+#pragma clang fp contract(off)
+  const int64_t c = a + (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (c >= b) return;
+  double bx[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  double M = 0, sx = 0, sy = 0, sz = 0;
+  double Q[6] = {0, 0, 0, 0, 0, 0};
+  double com[3];
+  if (C.nc[c] == 0) {
+    const int32_t f = C.first[c], e = f + C.n[c];
+    for (int32_t i = f; i < e; ++i) {
+      const float4 p = part[i];
+      const double x[3] = {p.x, p.y, p.z};
+      for (int k = 0; k < 3; ++k) {
+        bx[k] = hmin(bx[k], x[k]);
+        bx[3 + k] = hmax(bx[3 + k], x[k]);
+      }
+      const double w = p.w;
+      M += w;
+      sx += w * x[0];
+      sy += w * x[1];
+      sz += w * x[2];
+    }
+    com[0] = sx / M;
+    com[1] = sy / M;
+    com[2] = sz / M;
+    for (int32_t i = f; i < e; ++i) {
+      const float4 p = part[i];
+      const double d0 = p.x - com[0], d1 = p.y - com[1], d2 = p.z - com[2], w = p.w;
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      Q[0] += w * (3 * d0 * d0 - r2);
+      Q[1] += w * (3 * d1 * d1 - r2);
+      Q[2] += w * (3 * d2 * d2 - r2);
+      Q[3] += w * 3 * d0 * d1;
+      Q[4] += w * 3 * d0 * d2;
+      Q[5] += w * 3 * d1 * d2;
+    }
+  } else {
+    const int32_t f = C.fc[c], e = f + C.nc[c];
+    for (int32_t ch = f; ch < e; ++ch) {
+      const double* cb = box + 6 * (int64_t)ch;
+      const double* cq = mp64 + 10 * (int64_t)ch;
+      for (int k = 0; k < 3; ++k) {
+        bx[k] = hmin(bx[k], cb[k]);
+        bx[3 + k] = hmax(bx[3 + k], cb[3 + k]);
+      }
+      M += cq[0];
+      sx += cq[0] * cq[1];
+      sy += cq[0] * cq[2];
+      sz += cq[0] * cq[3];
+    }
+    com[0] = sx / M;
+    com[1] = sy / M;
+    com[2] = sz / M;
+    for (int32_t ch = f; ch < e; ++ch) {
+      const double* cq = mp64 + 10 * (int64_t)ch;
+      const double d0 = cq[1] - com[0], d1 = cq[2] - com[1], d2 = cq[3] - com[2], w = cq[0];
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      Q[0] += cq[4] + w * (3 * d0 * d0 - r2);
+      Q[1] += cq[5] + w * (3 * d1 * d1 - r2);
+      Q[2] += cq[6] + w * (3 * d2 * d2 - r2);
+      Q[3] += cq[7] + w * 3 * d0 * d1;
+      Q[4] += cq[8] + w * 3 * d0 * d2;
+      Q[5] += cq[9] + w * 3 * d1 * d2;
+    }
+  }
+  double* o = box + 6 * c;
+  for (int k = 0; k < 6; ++k) o[k] = bx[k];
+  double* q = mp64 + 10 * c;
+  q[0] = M;
+  for (int k = 0; k < 3; ++k) q[1 + k] = com[k];
+  for (int k = 0; k < 6; ++k) q[4 + k] = Q[k];
+}
+
+// FP32 images of every cell: topology, boundary (centre of the tight box,
+// side = largest extent; the device copy carries the leaf flag in the side's
+// sign bit), walk record, moments, and the learned criterion's cell features
+// with the host's FP32 expressions.
+__global__ void images_kernel(Cells C, int64_t nc, const double* __restrict__ box,
+                              const double* __restrict__ mp64, int4* __restrict__ topo,
+                              float4* __restrict__ geo_host, float4* __restrict__ geo,
+                              float4* __restrict__ wrec, float4* __restrict__ mp,
+                              float4* __restrict__ fcell) {
+#pragma clang fp contract(off)
+  const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (c >= nc) return;
+  const int4 tp = make_int4(C.fc[c], C.nc[c], C.first[c], C.n[c]);
+  topo[c] = tp;
+  const double* bx = box + 6 * c;
+  double l = 0;
+  float g[3];
+  for (int k = 0; k < 3; ++k) {
+    g[k] = (float)((bx[k] + bx[3 + k]) * 0.5);
+    l = hmax(l, bx[3 + k] - bx[k]);
+  }
+  const float lf = (float)l;
+  geo_host[c] = make_float4(g[0], g[1], g[2], lf);
+  const float4 gd = make_float4(g[0], g[1], g[2], tp.y == 0 ? -lf : lf);
+  geo[c] = gd;
+  wrec[2 * c] = gd;
+  wrec[2 * c + 1] = make_float4(__int_as_float(tp.x), __int_as_float(tp.y), __int_as_float(tp.z),
+                                __int_as_float(tp.w));
+  const double* q = mp64 + 10 * c;
+  const float m[10] = {(float)q[1], (float)q[2], (float)q[3], (float)q[0], (float)q[4],
+                       (float)q[5], (float)q[6], (float)q[7], (float)q[8], (float)q[9]};
+  mp[3 * c] = make_float4(m[0], m[1], m[2], m[3]);
+  mp[3 * c + 1] = make_float4(m[4], m[5], m[6], m[7]);
+  mp[3 * c + 2] = make_float4(m[8], m[9], 0.0f, 0.0f);
+  const float mtot = (float)mp64[0];
+  const float M = m[3];
+  const float qn = sqrtf((m[4] * m[4] + m[5] * m[5] + m[6] * m[6]) +
+                         2.0f * (m[7] * m[7] + m[8] * m[8] + m[9] * m[9]));
+  float s2 = 0.0f;
+  for (int k = 0; k < 3; ++k) {
+    const float d = m[k] - g[k];
+    s2 += d * d;
+  }
+  fcell[2 * c] = make_float4(log10f(M / mtot) / 3.0f, qn / (M * lf * lf),
+                             (float)(bx[3] - bx[0]) / lf, (float)(bx[4] - bx[1]) / lf);
+  fcell[2 * c + 1] = make_float4((float)(bx[5] - bx[2]) / lf,
+                                 log2f(1.0f + (float)C.depth[c]) / log2f(22.0f), sqrtf(s2) / lf,
+                                 0.0f);
+}
+
+// Groups: the maximal cells with at most n_group particles, or leaves; their
+// particle ranges partition the particles, so marking each group at its first
+// particle and compacting orders them by first particle.
+__global__ void group_mark_kernel(Cells C, int64_t nc, int n_group, int32_t* __restrict__ at) {
+  const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (c >= nc) return;
+  const bool cand = C.n[c] <= n_group || C.nc[c] == 0;
+  const bool top = c == 0 || C.n[C.parent[c]] > n_group;
+  if (cand && top) at[C.first[c]] = (int32_t)c;
+}
+
+__global__ void flag_kernel(const int32_t* __restrict__ at, int64_t n, int32_t* __restrict__ f) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < n) f[i] = at[i] >= 0;
+}
+
+__global__ void group_fill_kernel(const int32_t* __restrict__ at, const int32_t* __restrict__ f,
+                                  const int32_t* __restrict__ pre, int64_t n, Cells C,
+                                  const double* __restrict__ box, int32_t* __restrict__ groups,
+                                  int4* __restrict__ ginfo, float4* __restrict__ gbox,
+                                  int32_t* __restrict__ nchunk) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n || !f[i]) return;
+  const int64_t g = pre[i];
+  const int32_t c = at[i];
+  groups[g] = c;
+  ginfo[g] = make_int4(C.first[c], C.n[c], c, 0);
+  const double* bx = box + 6 * (int64_t)c;
+  gbox[2 * g] = make_float4((float)bx[0], (float)bx[1], (float)bx[2], 0.0f);
+  gbox[2 * g + 1] = make_float4((float)bx[3], (float)bx[4], (float)bx[5], 0.0f);
+  nchunk[g] = (C.n[c] + kChunk - 1) / kChunk;
+}
+
+__global__ void work_kernel(const int32_t* __restrict__ nchunk, const int32_t* __restrict__ pre,
+                            int64_t ng, int2* __restrict__ work) {
+  const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (g >= ng) return;
+  for (int k = 0; k < nchunk[g]; ++k) work[pre[g] + k] = make_int2((int32_t)g, k * kChunk);
+}
+
+// Scratch allocations of one build, freed on every exit.
+struct Scratch {
+  std::vector<void*> p;
+  ~Scratch() {
+    for (void* q : p) hipFree(q);
+  }
+  template <typename T>
+  T* get(int64_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>((size_t)count * sizeof(T), 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    p.push_back(q);
+    return static_cast<T*>(q);
+  }
+};
+
+template <typename T>
+int exclusive_sum(const T* in, T* out, int64_t n, Scratch& S, hipStream_t s) {
+  size_t bytes = 0;
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, s) != hipSuccess) return -1;
+  void* tmp = S.get<char>((int64_t)bytes);
+  if (!tmp) return -2;
+  return hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, (int)n, s) == hipSuccess ? 0 : -1;
+}
+
+}  // namespace
+
+int build_device_tree(const float* pos_h, const float* mass_h, int64_t n, int n_leaf, int n_group,
+                      HostTree& h, DevTree& dt, DeviceArrays& out, DevAlloc& alloc, void* stream,
+                      std::string& err) {
+  hipStream_t s = (hipStream_t)stream;
+  Scratch S;
+  auto fail = [&](const char* what) {
+    err = what;
+    return -1;
+  };
+  h = HostTree();
+  h.n = n;
+  h.n_leaf = n_leaf;
+  h.n_group = n_group;
+
+  // Inputs on the device.
+  float* pos = S.get<float>(3 * n);
+  float* mass = S.get<float>(n);
+  if (!pos || !mass) return fail("device allocation failed");
+  if (hipMemcpyAsync(pos, pos_h, (size_t)n * 12, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(mass, mass_h, (size_t)n * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail("input upload failed");
+
+  // Root cube (the host's rule on the device's bounding box).
+  const int nbb = (int)std::min<int64_t>(1024, blocks(n));
+  float* bbp = S.get<float>(6 * nbb);
+  if (!bbp) return fail("device allocation failed");
+  bbox_kernel<<<nbb, kT, 0, s>>>(pos, n, bbp);
+  std::vector<float> bbh((size_t)6 * nbb);
+  if (hipMemcpyAsync(bbh.data(), bbp, bbh.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail("bounding box failed");
+  double lo[3], hi[3];
+  for (int k = 0; k < 3; ++k) {
+    float a = bbh[k], b = bbh[3 + k];
+    for (int i = 1; i < nbb; ++i) {
+      a = std::min(a, bbh[6 * i + k]);
+      b = std::max(b, bbh[6 * i + 3 + k]);
+    }
+    lo[k] = a;
+    hi[k] = b;
+  }
+  root_cube(lo, hi, h.corner, &h.side);
+
+  // Keys and the stable sort (ties keep the input order).
+  const double step = std::ldexp(h.side, -kMaxDepth), inv = std::ldexp(1.0 / h.side, kMaxDepth);
+  uint64_t* key = S.get<uint64_t>(n);
+  uint64_t* key2 = S.get<uint64_t>(n);
+  int32_t* idx = S.get<int32_t>(n);
+  int32_t* perm = nullptr;
+  if (!key || !key2 || !idx || alloc.alloc((void**)&perm, (size_t)n * 4)) return fail("device allocation failed");
+  keys_kernel<<<blocks(n), kT, 0, s>>>(pos, n, h.corner[0], h.corner[1], h.corner[2], step, inv,
+                                       key, idx);
+  size_t sbytes = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, sbytes, key, key2, idx, perm, (int)n, 0, 63, s) !=
+      hipSuccess)
+    return fail("sort failed");
+  void* stmp = S.get<char>((int64_t)sbytes);
+  if (!stmp) return fail("device allocation failed");
+  if (hipcub::DeviceRadixSort::SortPairs(stmp, sbytes, key, key2, idx, perm, (int)n, 0, 63, s) !=
+      hipSuccess)
+    return fail("sort failed");
+
+  // Level-synchronous subdivision; cell arrays grow as needed.
+  int64_t cap = 2 * n + 64;
+  Cells C{};
+  auto grow = [&](int64_t need) -> bool {
+    if (need <= cap && C.first) return true;
+    const int64_t nc2 = C.first ? std::max(need, cap + cap / 2) : need;
+    Cells D{S.get<int32_t>(nc2), S.get<int32_t>(nc2), S.get<int32_t>(nc2),
+            S.get<int32_t>(nc2), S.get<int32_t>(nc2), S.get<int32_t>(nc2)};
+    if (!D.first || !D.n || !D.depth || !D.parent || !D.fc || !D.nc) return false;
+    if (C.first) {
+      int32_t* src[6] = {C.first, C.n, C.depth, C.parent, C.fc, C.nc};
+      int32_t* dst[6] = {D.first, D.n, D.depth, D.parent, D.fc, D.nc};
+      for (int k = 0; k < 6; ++k)
+        if (hipMemcpyAsync(dst[k], src[k], (size_t)cap * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+          return false;
+    }
+    C = D;
+    cap = nc2;
+    return true;
+  };
+  if (!grow(cap)) return fail("device allocation failed");
+  const int32_t root[6] = {0, (int32_t)n, 0, -1, -1, 0};
+  int32_t* rdst[6] = {C.first, C.n, C.depth, C.parent, C.fc, C.nc};
+  for (int k = 0; k < 6; ++k)
+    if (hipMemcpyAsync(rdst[k], &root[k], 4, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail("root upload failed");
+  std::vector<int64_t> level_beg{0};
+  int64_t lbeg = 0, lend = 1;
+  for (int L = 0; lbeg < lend; ++L) {
+    const int64_t m = lend - lbeg;
+    Scratch LS;
+    int32_t* bd = LS.get<int32_t>(9 * m);
+    int32_t* nkid = LS.get<int32_t>(m + 1);
+    int32_t* pre = LS.get<int32_t>(m + 1);
+    if (!bd || !nkid || !pre) return fail("device allocation failed");
+    split_kernel<<<blocks(m), kT, 0, s>>>(C, key2, lbeg, m, L, n_leaf, bd, nkid);
+    if (hipMemsetAsync(nkid + m, 0, 4, s) != hipSuccess) return fail("memset failed");
+    if (exclusive_sum(nkid, pre, m + 1, LS, s)) return fail("scan failed");
+    int32_t total = 0;
+    if (hipMemcpyAsync(&total, pre + m, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail("level count failed");
+    if (total > 0) {
+      if (!grow(lend + total)) return fail("device allocation failed");
+      emit_kernel<<<blocks(m), kT, 0, s>>>(C, lbeg, lend, m, L, bd, nkid, pre);
+    }
+    h.max_level_cells = std::max(h.max_level_cells, m);
+    if (total > 0) h.max_depth = L + 1;
+    lbeg = lend;
+    lend += total;
+    level_beg.push_back(lbeg);  // level L spans [level_beg[L], level_beg[L + 1])
+    if (hipStreamSynchronize(s) != hipSuccess) return fail("subdivision failed");
+  }
+  const int64_t nc = lend;
+
+  // Persistent device arrays of the tree.
+  auto A = [&](void** p, size_t bytes) { return alloc.alloc(p, bytes) == 0; };
+  float4* part = nullptr;
+  int32_t* iperm = nullptr;
+  if (!A((void**)&part, (size_t)n * 16) || !A((void**)&iperm, (size_t)n * 4))
+    return fail("device allocation failed");
+  gather_kernel<<<blocks(n), kT, 0, s>>>(pos, mass, perm, n, part, iperm);
+
+  double* box = nullptr;
+  double* mp64 = nullptr;
+  if (!A((void**)&box, (size_t)nc * 48) || !A((void**)&mp64, (size_t)nc * 80))
+    return fail("device allocation failed");
+  for (int L = h.max_depth; L >= 0; --L) {
+    const int64_t a = level_beg[L], b = level_beg[L + 1];
+    if (b > a) moments_kernel<<<blocks(b - a), kT, 0, s>>>(C, part, a, b, box, mp64);
+  }
+  int4* topo = nullptr;
+  float4 *geo_host = nullptr, *geo = nullptr, *wrec = nullptr, *mp = nullptr, *fcell = nullptr;
+  int32_t* depth = nullptr;
+  if (!A((void**)&topo, (size_t)nc * 16) || !A((void**)&geo_host, (size_t)nc * 16) ||
+      !A((void**)&geo, (size_t)nc * 16) || !A((void**)&wrec, (size_t)nc * 32) ||
+      !A((void**)&mp, (size_t)nc * 48) || !A((void**)&fcell, (size_t)nc * 32) ||
+      !A((void**)&depth, (size_t)nc * 4))
+    return fail("device allocation failed");
+  images_kernel<<<blocks(nc), kT, 0, s>>>(C, nc, box, mp64, topo, geo_host, geo, wrec, mp, fcell);
+  if (hipMemcpyAsync(depth, C.depth, (size_t)nc * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail("copy failed");
+
+  // Groups and work chunks.
+  int32_t* at = S.get<int32_t>(n);
+  int32_t* f = S.get<int32_t>(n + 1);
+  int32_t* fpre = S.get<int32_t>(n + 1);
+  if (!at || !f || !fpre) return fail("device allocation failed");
+  if (hipMemsetAsync(at, 0xff, (size_t)n * 4, s) != hipSuccess) return fail("memset failed");
+  group_mark_kernel<<<blocks(nc), kT, 0, s>>>(C, nc, n_group, at);
+  flag_kernel<<<blocks(n), kT, 0, s>>>(at, n, f);
+  if (hipMemsetAsync(f + n, 0, 4, s) != hipSuccess) return fail("memset failed");
+  if (exclusive_sum(f, fpre, n + 1, S, s)) return fail("scan failed");
+  int32_t ng = 0;
+  if (hipMemcpyAsync(&ng, fpre + n, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail("group count failed");
+  int32_t* groups = nullptr;
+  int4* ginfo = nullptr;
+  float4* gbox = nullptr;
+  if (!A((void**)&groups, (size_t)ng * 4) || !A((void**)&ginfo, (size_t)ng * 16) ||
+      !A((void**)&gbox, (size_t)ng * 32))
+    return fail("device allocation failed");
+  int32_t* nchunk = S.get<int32_t>(ng + 1);
+  int32_t* cpre = S.get<int32_t>(ng + 1);
+  if (!nchunk || !cpre) return fail("device allocation failed");
+  group_fill_kernel<<<blocks(n), kT, 0, s>>>(at, f, fpre, n, C, box, groups, ginfo, gbox, nchunk);
+  if (hipMemsetAsync(nchunk + ng, 0, 4, s) != hipSuccess) return fail("memset failed");
+  if (exclusive_sum(nchunk, cpre, (int64_t)ng + 1, S, s)) return fail("scan failed");
+  int32_t nw = 0;
+  if (hipMemcpyAsync(&nw, cpre + ng, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail("work count failed");
+  int2* work = nullptr;
+  if (!A((void**)&work, (size_t)nw * 8)) return fail("device allocation failed");
+  work_kernel<<<blocks(ng), kT, 0, s>>>(nchunk, cpre, ng, work);
+
+  // Host copies the rest of the library needs now (the remaining arrays are
+  // fetched on export).
+  h.depth.resize(nc);
+  h.topo.resize((size_t)nc * 4);
+  h.groups.resize(ng);
+  h.work.resize((size_t)nw * 2);
+  if (hipMemcpyAsync(h.depth.data(), depth, (size_t)nc * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(h.topo.data(), topo, (size_t)nc * 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(h.groups.data(), groups, (size_t)ng * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(h.work.data(), work, (size_t)nw * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail("host copies failed");
+
+  dt.part = reinterpret_cast<const float*>(part);
+  dt.perm = perm;
+  dt.topo = reinterpret_cast<const int32_t*>(topo);
+  dt.geo = reinterpret_cast<const float*>(geo);
+  dt.wrec = reinterpret_cast<const float*>(wrec);
+  dt.fcell = reinterpret_cast<const float*>(fcell);
+  dt.iperm = iperm;
+  dt.mp = reinterpret_cast<const float*>(mp);
+  dt.ginfo = reinterpret_cast<const int32_t*>(ginfo);
+  dt.gbox = reinterpret_cast<const float*>(gbox);
+  dt.work = reinterpret_cast<const int32_t*>(work);
+  dt.n = n;
+  dt.nc = nc;
+  dt.ng = ng;
+  dt.nw = nw;
+  out.box = box;
+  out.mp64 = mp64;
+  out.geo_host = reinterpret_cast<const float*>(geo_host);
+  out.depth = depth;
+  return 0;
+}
+
+}  // namespace octgrav

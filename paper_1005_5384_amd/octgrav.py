@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libocgrav.so")
 
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY = 0, -1, -2, -3, -4
 BUILD_HOST_ONLY = 1
+BUILD_DEVICE = 2
 PLAIN_SUM = 1
 TIMED = 2
 TWO_PASS = 4
@@ -122,14 +123,15 @@ def _ptr(a):
 class Tree:
     """A built tree (host FP64 build + device upload) and its force calls."""
 
-    def __init__(self, pos, mass, n_leaf=16, n_group=64, host_only=False):
+    def __init__(self, pos, mass, n_leaf=16, n_group=64, host_only=False, device_build=False):
         pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
         mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
         self.n = pos.shape[0]
         if mass.shape[0] != self.n:
             raise ValueError("pos and mass disagree on n")
+        flags = (BUILD_HOST_ONLY if host_only else 0) | (BUILD_DEVICE if device_build else 0)
         h = lib().octgrav_build_tree_ex(_ptr(pos), _ptr(mass), self.n, int(n_leaf), int(n_group),
-                                        BUILD_HOST_ONLY if host_only else 0)
+                                        flags)
         if not h:
             raise OctgravError(EINVAL, last_error())
         self._h = C.c_void_p(h)

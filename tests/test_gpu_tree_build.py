@@ -1,0 +1,74 @@
+"""The tree built on the GPU is the host build bit for bit: every exported
+array (order, topology, FP32 and FP64 geometry and moments, depths, groups,
+root cube) and therefore the lists and forces."""
+import numpy as np
+import pytest
+
+from paper_1005_5384_amd import octgrav as og
+from paper_1005_5384_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _same_tree(pos, m, n_leaf=16, n_group=64):
+    H = og.Tree(pos, m, n_leaf, n_group)
+    D = og.Tree(pos, m, n_leaf, n_group, device_build=True)
+    assert D.stats == H.stats
+    eh, ed = H.export(), D.export()
+    for k in eh:
+        assert eh[k].dtype == ed[k].dtype and eh[k].shape == ed[k].shape, k
+        assert np.array_equal(eh[k].view(np.uint8), ed[k].view(np.uint8)), k
+    return H, D
+
+
+@pytest.mark.parametrize("n,n_leaf,n_group,seed", [(1, 16, 64, 0), (2, 1, 1, 1), (100, 1, 1, 2),
+                                                   (1000, 4, 8, 3), (4097, 16, 64, 4),
+                                                   (16384, 64, 1024, 5), (16384, 16, 64, 6)])
+def test_device_build_matches_host_plummer(n, n_leaf, n_group, seed):
+    _torch()
+    pos, m = W.plummer(n, seed)
+    _same_tree(pos, m, n_leaf, n_group)
+
+
+def test_device_build_coincident_and_plane_ties():
+    _torch()
+    rng = np.random.default_rng(9)
+    pos = np.concatenate([np.zeros((150, 3)), rng.integers(-4, 5, (400, 3)) * 0.25,
+                          rng.normal(0, 1, (200, 3))]).astype(np.float32)
+    m = rng.uniform(0.5, 2.0, pos.shape[0]).astype(np.float32)
+    H, D = _same_tree(pos, m, 16, 64)
+    assert H.stats["max_depth"] == 21
+
+
+def test_device_build_same_lists_and_forces():
+    torch = _torch()
+    pos, m = W.make("plummer1m")
+    H, D = _same_tree(pos, m)
+    for theta in (0.5, 0.75):
+        ah, ph = H.forces(theta, 1e-3)
+        ad, pd = D.forces(theta, 1e-3)
+        assert torch.equal(ah, ad) and torch.equal(ph, pd)
+    for a, b in zip(H.lists(0.5), D.lists(0.5)):
+        assert np.array_equal(a, b)
+
+
+def test_device_build_clumps():
+    _torch()
+    pos, m = W.make("clumps4m", n=1 << 20)
+    _same_tree(pos, m, 32, 64)
+
+
+def test_device_build_rejects_bad_input():
+    _torch()
+    pos, m = W.plummer(100, 1)
+    pos[5, 1] = np.nan
+    with pytest.raises(og.OctgravError):
+        og.Tree(pos, m, device_build=True)
+    with pytest.raises(og.OctgravError):
+        og.Tree(W.plummer(100, 1)[0], m, host_only=True, device_build=True)
