@@ -216,6 +216,15 @@ def main():
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     log(f"bench: tree built+uploaded in {t_build:.3f} s: {T.stats}")
+    # the same tree built on the GPU (bit-identical; timed, then released)
+    og.Tree(pos[:1024], m[:1024], w["n_leaf"], 64, device_build=True)  # first-use setup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Tdev = og.Tree(pos, m, w["n_leaf"], 64, device_build=True)
+    torch.cuda.synchronize()
+    t_dev_build = time.perf_counter() - t0
+    del Tdev
+    log(f"bench: device build {t_dev_build:.4f} s")
     acc = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     pot = torch.empty(n, dtype=torch.float32, device="cuda")
     theta, eps = args.theta, w["eps"]
@@ -279,6 +288,7 @@ def main():
         "interactions": counts,
         "phases_ms": ph,
         "host_build_upload_s": t_build,
+        "device_build_s": t_dev_build,
         "tree": T.stats,
     }
     if args.mac == "learned":
