@@ -268,6 +268,36 @@ int octgrav_mac_stats(octgrav_tree* t, int64_t out[2]);
 int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells, float* scores,
                       int64_t cap, int64_t* n_out, int32_t* fell_back);
 
+/*
+ * ---- Time integration (the step after the force call: the paper's science
+ * runs advance a particle system with the tree code).
+ *
+ * A particle system on the device, advanced with kick-drift-kick leapfrog
+ * (v += a dt/2, x += v dt, new tree and forces, v += a dt/2) in FP32; the
+ * tree is rebuilt on the GPU from the drifted positions every step (as
+ * OCTGRAV_BUILD_DEVICE, inputs never leave the device).
+ */
+typedef struct octgrav_sim octgrav_sim;
+
+/* Copies pos, vel (host, n x 3 FP32) and mass (host, n FP32) to the device;
+ * input rules as octgrav_build_tree_ex, velocities finite.  NULL on failure. */
+octgrav_sim* octgrav_sim_create(const float* pos, const float* vel, const float* mass, int64_t n,
+                                int32_t n_leaf, int32_t n_group);
+void octgrav_sim_free(octgrav_sim* s); /* NULL-safe */
+int octgrav_sim_set_stream(octgrav_sim* s, void* hip_stream);
+/* steps leapfrog steps of length dt with opening angle theta and softening
+ * eps (forces at the current positions are computed first when missing or
+ * when theta / eps changed; steps = 0 only does that).  Synchronous. */
+int octgrav_sim_run(octgrav_sim* s, float theta, float eps, float dt, int32_t steps);
+/* out = {K, W, E = K + W, sum m vx, sum m vy, sum m vz} in FP64: K = 1/2 sum
+ * m v^2, W = 1/2 sum m phi with the last forces (potentials self-excluded). */
+int octgrav_sim_energy(octgrav_sim* s, double out[6]);
+/* Host copies of positions, velocities and the last accelerations (each
+ * n x 3 FP32, any may be NULL). */
+int octgrav_sim_state(const octgrav_sim* s, float* pos, float* vel, float* acc);
+/* Last run, per step: total, tree build and force milliseconds (host clock). */
+int octgrav_sim_timings(const octgrav_sim* s, double out[3]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,6 +44,8 @@ def lib():
             f.argtypes = [vp, C.c_float, vp, vp, vp, vp, vp, vp]
         L.orc_forces.argtypes = [vp, C.c_float, C.c_float, vp, C.c_int64, _f64p, vp]
         L.orc_counts.argtypes = [vp, C.c_float, _i64p]
+        L.orc_leapfrog.argtypes = [_f64p, _f64p, _f64p, C.c_int64, C.c_double, C.c_double,
+                                   C.c_int64, _f64p, _f64p, vp]
         L.orc_forces_lists.argtypes = [vp, C.c_float, _i64p, _i32p, _i64p, _i32p, vp, C.c_int64,
                                        _f64p, vp]
         L.orc_diagnostics.argtypes = [_f32p, _f64p, vp, C.c_int64, _f64p]
@@ -255,6 +257,20 @@ def _forces_lists(self, lists, eps, groups=None):
 
 
 Tree.forces_lists = _forces_lists
+
+
+def leapfrog(pos, vel, mass, eps, dt, steps):
+    """FP64 kick-drift-kick leapfrog with direct-sum forces: (pos, vel,
+    energies [steps + 1, 2] = (K, W))."""
+    pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+    vel = np.ascontiguousarray(vel, np.float64).reshape(-1, 3)
+    mass = np.ascontiguousarray(mass, np.float64)
+    n = pos.shape[0]
+    po, vo = np.zeros_like(pos), np.zeros_like(vel)
+    en = np.zeros((steps + 1, 2))
+    assert lib().orc_leapfrog(pos, vel, mass, n, float(eps), float(dt), int(steps), po, vo,
+                              _ptr(en)) == 0
+    return po, vo, en
 
 
 def mlp_params() -> int:

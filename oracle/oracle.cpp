@@ -593,6 +593,68 @@ int orc_forces_lists(const void* h, float eps, const int64_t* c_off, const int32
   return 0;
 }
 
+// Kick-drift-kick leapfrog with FP64 direct-sum accelerations (the plain
+// definitions: Plummer-softened Newtonian gravity, G = 1; v += a dt/2,
+// x += v dt, v += a dt/2 with a from the new positions).  State in FP64;
+// energy[2k], energy[2k + 1] = K, W after k steps (k = 0 .. steps).
+namespace {
+void acc64(const std::vector<double>& x, const double* m, int64_t n, double eps2,
+           std::vector<double>& a, double* W) {
+  double w = 0;
+#pragma omp parallel for schedule(static) reduction(+ : w)
+  for (int64_t i = 0; i < n; ++i) {
+    double ax = 0, ay = 0, az = 0, ph = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double dx = x[3 * j] - x[3 * i], dy = x[3 * j + 1] - x[3 * i + 1],
+                   dz = x[3 * j + 2] - x[3 * i + 2];
+      const double r2 = dx * dx + dy * dy + dz * dz + eps2, ri = 1.0 / std::sqrt(r2);
+      const double f = m[j] * ri * ri * ri;
+      ax += f * dx;
+      ay += f * dy;
+      az += f * dz;
+      ph -= m[j] * ri;
+    }
+    a[3 * i] = ax;
+    a[3 * i + 1] = ay;
+    a[3 * i + 2] = az;
+    w += 0.5 * m[i] * ph;
+  }
+  *W = w;
+}
+double kinetic(const std::vector<double>& v, const double* m, int64_t n) {
+  double k = 0;
+  for (int64_t i = 0; i < n; ++i)
+    k += 0.5 * m[i] * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2]);
+  return k;
+}
+}  // namespace
+
+int orc_leapfrog(const double* pos, const double* vel, const double* mass, int64_t n, double eps,
+                 double dt, int64_t steps, double* pos_out, double* vel_out, double* energy) {
+  std::vector<double> x(pos, pos + 3 * n), v(vel, vel + 3 * n), a(3 * n);
+  const double eps2 = eps * eps;
+  double W;
+  acc64(x, mass, n, eps2, a, &W);
+  if (energy) {
+    energy[0] = kinetic(v, mass, n);
+    energy[1] = W;
+  }
+  for (int64_t s = 0; s < steps; ++s) {
+    for (int64_t i = 0; i < 3 * n; ++i) v[i] += 0.5 * dt * a[i];
+    for (int64_t i = 0; i < 3 * n; ++i) x[i] += dt * v[i];
+    acc64(x, mass, n, eps2, a, &W);
+    for (int64_t i = 0; i < 3 * n; ++i) v[i] += 0.5 * dt * a[i];
+    if (energy) {
+      energy[2 * (s + 1)] = kinetic(v, mass, n);
+      energy[2 * (s + 1) + 1] = W;
+    }
+  }
+  std::copy(x.begin(), x.end(), pos_out);
+  std::copy(v.begin(), v.end(), vel_out);
+  return 0;
+}
+
 // Interaction counts of the selected groups: per group |C_g|, |L_g| and the
 // number of source particles in L_g.
 int orc_counts(const void* h, float theta, int64_t* out3) {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cmath>
 #include <cstring>
@@ -403,8 +404,8 @@ octgrav_tree* octgrav_build_tree_ex(const float* pos, const float* mass, int64_t
         return nullptr;
       }
       octgrav_tree* t = new octgrav_tree;
-      if (build_device_tree(pos, mass, n, n_leaf, n_group, t->h, t->dt, t->darr, *t, t->stream,
-                            err) != 0) {
+      if (build_device_tree(pos, mass, false, n, n_leaf, n_group, t->h, t->dt, t->darr, *t,
+                            t->stream, err) != 0) {
         std::string keep = g_err.empty() ? err : g_err;
         delete t;
         fail(OCTGRAV_EHIP, keep);
@@ -988,6 +989,193 @@ int octgrav_mlp_adam(octgrav_mlp* m, float lr, float beta1, float beta2, float e
       launch_mlp_pack((const float*)m->P, m->pk, m->stream) ||
       hipStreamSynchronize(m->stream) != hipSuccess)
     return fail(OCTGRAV_EHIP, "Adam step failed");
+  return OCTGRAV_OK;
+}
+
+// ------------------------------------------------------------------ integration
+
+// A particle system on the device, integrated with kick-drift-kick leapfrog;
+// the tree is rebuilt on the GPU from the drifted positions every step.
+struct octgrav_sim {
+  int64_t n = 0;
+  int n_leaf = 16, n_group = 64;
+  hipStream_t stream = nullptr;
+  float *pos = nullptr, *vel = nullptr, *mass = nullptr, *acc = nullptr, *pot = nullptr;
+  double *kpart = nullptr, *kout = nullptr;
+  octgrav_tree* tree = nullptr;
+  bool have_forces = false;
+  float theta = -1.0f, eps = -1.0f;
+  double timings[3] = {0, 0, 0};  // last run: ms per step, of which tree build, forces
+
+  ~octgrav_sim() {
+    if (tree) octgrav_free(tree);
+    for (void* p : {(void*)pos, (void*)vel, (void*)mass, (void*)acc, (void*)pot, (void*)kpart,
+                    (void*)kout})
+      if (p) hipFree(p);
+  }
+
+  // Tree of the current positions and the forces on them.
+  int rebuild_and_force(double* t_build, double* t_force) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (tree) {
+      octgrav_free(tree);
+      tree = nullptr;
+    }
+    octgrav_tree* t = new octgrav_tree;
+    t->stream = stream;
+    std::string err;
+    if (build_device_tree(pos, mass, true, n, n_leaf, n_group, t->h, t->dt, t->darr, *t, stream,
+                          err) != 0) {
+      std::string keep = g_err.empty() ? err : g_err;
+      delete t;
+      return fail(err.find("must be") != std::string::npos ? OCTGRAV_EINVAL : OCTGRAV_EHIP, keep);
+    }
+    t->host_partial = true;
+    if (int rc = t->alloc_walk_buffers()) {
+      delete t;
+      return rc;
+    }
+    tree = t;
+    auto t1 = std::chrono::steady_clock::now();
+    if (int rc = octgrav_forces_ex(tree, theta, eps, acc, pot, 0)) return rc;
+    auto t2 = std::chrono::steady_clock::now();
+    *t_build += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    *t_force += std::chrono::duration<double, std::milli>(t2 - t1).count();
+    have_forces = true;
+    return OCTGRAV_OK;
+  }
+};
+
+octgrav_sim* octgrav_sim_create(const float* pos, const float* vel, const float* mass, int64_t n,
+                                int32_t n_leaf, int32_t n_group) {
+  g_err.clear();
+  std::string err;
+  if (!vel) {
+    fail(OCTGRAV_EINVAL, "vel must be non-NULL");
+    return nullptr;
+  }
+  if (!validate_inputs(pos, mass, n, n_leaf, n_group, err)) {
+    fail(OCTGRAV_EINVAL, err);
+    return nullptr;
+  }
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(vel[i])) {
+      fail(OCTGRAV_EINVAL, "velocities must be finite");
+      return nullptr;
+    }
+  octgrav_sim* s = new (std::nothrow) octgrav_sim;
+  if (!s) {
+    fail(OCTGRAV_ENOMEM, "out of host memory");
+    return nullptr;
+  }
+  s->n = n;
+  s->n_leaf = n_leaf;
+  s->n_group = n_group;
+  auto A = [&](void** p, size_t bytes) {
+    if (alloc_fault() || hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return false;
+    }
+    return true;
+  };
+  if (!A((void**)&s->pos, n * 12) || !A((void**)&s->vel, n * 12) || !A((void**)&s->mass, n * 4) ||
+      !A((void**)&s->acc, n * 12) || !A((void**)&s->pot, n * 4) ||
+      !A((void**)&s->kpart, kinetic_scratch_entries() * 8) || !A((void**)&s->kout, 32)) {
+    delete s;
+    fail(OCTGRAV_ENOMEM, "device allocation failed");
+    return nullptr;
+  }
+  if (hipMemcpy(s->pos, pos, n * 12, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(s->vel, vel, n * 12, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(s->mass, mass, n * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    delete s;
+    fail(OCTGRAV_EHIP, "state upload failed");
+    return nullptr;
+  }
+  return s;
+}
+
+void octgrav_sim_free(octgrav_sim* s) { delete s; }
+
+int octgrav_sim_set_stream(octgrav_sim* s, void* hip_stream) {
+  if (!s) return fail(OCTGRAV_EINVAL, "NULL handle");
+  s->stream = (hipStream_t)hip_stream;
+  if (s->tree) s->tree->stream = s->stream;
+  return OCTGRAV_OK;
+}
+
+int octgrav_sim_run(octgrav_sim* s, float theta, float eps, float dt, int32_t steps) {
+  g_err.clear();
+  if (!s) return fail(OCTGRAV_EINVAL, "NULL handle");
+  if (!(theta >= 0.0f && theta <= 1.0f)) return fail(OCTGRAV_EINVAL, "theta must be in [0, 1]");
+  if (!(eps > 0.0f) || !std::isfinite(eps)) return fail(OCTGRAV_EINVAL, "eps must be finite and > 0");
+  if (!std::isfinite(dt) || steps < 0) return fail(OCTGRAV_EINVAL, "bad dt or steps");
+  try {
+    double tb = 0, tf = 0;
+    auto t0 = std::chrono::steady_clock::now();
+    if (!s->have_forces || theta != s->theta || eps != s->eps) {
+      s->theta = theta;
+      s->eps = eps;
+      if (int rc = s->rebuild_and_force(&tb, &tf)) return rc;
+      tb = tf = 0;
+      t0 = std::chrono::steady_clock::now();
+    }
+    for (int32_t k = 0; k < steps; ++k) {
+      if (launch_kick(s->vel, s->acc, s->n, 0.5f * dt, s->stream) ||
+          launch_drift(s->pos, s->vel, s->n, dt, s->stream))
+        return fail(OCTGRAV_EHIP, "leapfrog launch failed");
+      if (int rc = s->rebuild_and_force(&tb, &tf)) return rc;
+      if (launch_kick(s->vel, s->acc, s->n, 0.5f * dt, s->stream))
+        return fail(OCTGRAV_EHIP, "leapfrog launch failed");
+    }
+    if (hipStreamSynchronize(s->stream) != hipSuccess)
+      return fail(OCTGRAV_EHIP, "device error during integration");
+    if (steps > 0) {
+      const double ms = std::chrono::duration<double, std::milli>(
+                            std::chrono::steady_clock::now() - t0).count();
+      s->timings[0] = ms / steps;
+      s->timings[1] = tb / steps;
+      s->timings[2] = tf / steps;
+    }
+    return OCTGRAV_OK;
+  } catch (const std::exception& e) {
+    return fail(OCTGRAV_EHIP, e.what());
+  }
+}
+
+int octgrav_sim_energy(octgrav_sim* s, double out[6]) {
+  g_err.clear();
+  if (!s || !out) return fail(OCTGRAV_EINVAL, "NULL argument");
+  if (!s->have_forces) return fail(OCTGRAV_EINVAL, "no forces yet: run at least once (steps may be 0)");
+  double k4[4], mom[3], w;
+  if (launch_kinetic(s->mass, s->vel, s->n, s->kpart, s->kout, s->stream) ||
+      hipMemcpyAsync(k4, s->kout, 32, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "kinetic energy failed");
+  if (int rc = octgrav_diagnostics(s->tree, mom, &w)) return rc;
+  out[0] = k4[0];
+  out[1] = w;
+  out[2] = k4[0] + w;
+  out[3] = k4[1];
+  out[4] = k4[2];
+  out[5] = k4[3];
+  return OCTGRAV_OK;
+}
+
+int octgrav_sim_state(const octgrav_sim* s, float* pos, float* vel, float* acc) {
+  if (!s) return fail(OCTGRAV_EINVAL, "NULL handle");
+  if (hipStreamSynchronize(s->stream) != hipSuccess ||
+      (pos && hipMemcpy(pos, s->pos, s->n * 12, hipMemcpyDeviceToHost) != hipSuccess) ||
+      (vel && hipMemcpy(vel, s->vel, s->n * 12, hipMemcpyDeviceToHost) != hipSuccess) ||
+      (acc && s->have_forces && hipMemcpy(acc, s->acc, s->n * 12, hipMemcpyDeviceToHost) != hipSuccess))
+    return fail(OCTGRAV_EHIP, "state copy-back failed");
+  return OCTGRAV_OK;
+}
+
+int octgrav_sim_timings(const octgrav_sim* s, double out[3]) {
+  if (!s || !out) return fail(OCTGRAV_EINVAL, "NULL argument");
+  for (int k = 0; k < 3; ++k) out[k] = s->timings[k];
   return OCTGRAV_OK;
 }
 

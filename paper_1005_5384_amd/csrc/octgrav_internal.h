@@ -168,9 +168,18 @@ struct DeviceArrays {
   const float* geo_host = nullptr; // [nc * 4]
   const int32_t* depth = nullptr;  // [nc]
 };
-int build_device_tree(const float* pos_h, const float* mass_h, int64_t n, int n_leaf, int n_group,
-                      HostTree& h, DevTree& dt, DeviceArrays& out, DevAlloc& alloc, void* stream,
-                      std::string& err);
+// Inputs are host arrays (copied) or, with inputs_on_device, device arrays
+// (checked on the device).
+int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_device, int64_t n,
+                      int n_leaf, int n_group, HostTree& h, DevTree& dt, DeviceArrays& out,
+                      DevAlloc& alloc, void* stream, std::string& err);
+
+// Leapfrog pieces: v += h a, x += dt v, and FP64 (1/2 sum m v^2, sum m v).
+int launch_kick(float* vel, const float* acc, int64_t n, float h, void* stream);
+int launch_drift(float* pos, const float* vel, int64_t n, float dt, void* stream);
+int launch_kinetic(const float* mass, const float* vel, int64_t n, double* part, double* out4,
+                   void* stream);
+int64_t kinetic_scratch_entries();
 
 int launch_diag(const DevTree& T, const float* acc, const float* pot, double* part_sums,
                 double* out4, void* stream);

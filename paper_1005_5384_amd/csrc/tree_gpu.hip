@@ -55,6 +55,23 @@ __global__ void bbox_kernel(const float* __restrict__ pos, int64_t n, float* __r
   if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// Input check of device-resident inputs: bit 1 = a position not finite or
+// |x| >= 2^60, bit 2 = a mass not finite or not > 0.
+__global__ void validate_kernel(const float* __restrict__ pos, const float* __restrict__ mass,
+                                int64_t n, int32_t* __restrict__ bad) {
+  int b = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    for (int k = 0; k < 3; ++k) {
+      const float v = pos[3 * i + k];
+      if (!(fabsf(v) < 0x1p60f)) b |= 1;  // also catches NaN
+    }
+    const float m = mass[i];
+    if (!(m > 0.0f) || !(m < INFINITY)) b |= 2;
+  }
+  if (__any(b & 1) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+  if (__any(b & 2) && (threadIdx.x & 63) == 0) atomicOr(bad, 2);
+}
+
 // The host's grid coordinate: floor, then exact against the grid planes.
 __device__ __forceinline__ uint32_t grid_coord(double x, double corner, double step,
                                                double inv_step) {
@@ -363,9 +380,9 @@ int exclusive_sum(const T* in, T* out, int64_t n, Scratch& S, hipStream_t s) {
 
 }  // namespace
 
-int build_device_tree(const float* pos_h, const float* mass_h, int64_t n, int n_leaf, int n_group,
-                      HostTree& h, DevTree& dt, DeviceArrays& out, DevAlloc& alloc, void* stream,
-                      std::string& err) {
+int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_device, int64_t n,
+                      int n_leaf, int n_group, HostTree& h, DevTree& dt, DeviceArrays& out,
+                      DevAlloc& alloc, void* stream, std::string& err) {
   hipStream_t s = (hipStream_t)stream;
   Scratch S;
   auto fail = [&](const char* what) {
@@ -377,13 +394,31 @@ int build_device_tree(const float* pos_h, const float* mass_h, int64_t n, int n_
   h.n_leaf = n_leaf;
   h.n_group = n_group;
 
-  // Inputs on the device.
-  float* pos = S.get<float>(3 * n);
-  float* mass = S.get<float>(n);
-  if (!pos || !mass) return fail("device allocation failed");
-  if (hipMemcpyAsync(pos, pos_h, (size_t)n * 12, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(mass, mass_h, (size_t)n * 4, hipMemcpyHostToDevice, s) != hipSuccess)
-    return fail("input upload failed");
+  // Inputs on the device (copied there, or checked there: finite positions
+  // with |x| < 2^60 and finite masses > 0, as the host build requires).
+  const float* pos = pos_in;
+  const float* mass = mass_in;
+  if (!inputs_on_device) {
+    float* p = S.get<float>(3 * n);
+    float* q = S.get<float>(n);
+    if (!p || !q) return fail("device allocation failed");
+    if (hipMemcpyAsync(p, pos_in, (size_t)n * 12, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(q, mass_in, (size_t)n * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail("input upload failed");
+    pos = p;
+    mass = q;
+  } else {
+    int32_t* bad = S.get<int32_t>(1);
+    if (!bad) return fail("device allocation failed");
+    int32_t hb = 0;
+    if (hipMemsetAsync(bad, 0, 4, s) != hipSuccess) return fail("memset failed");
+    validate_kernel<<<std::min<int64_t>(2048, blocks(n)), kT, 0, s>>>(pos, mass, n, bad);
+    if (hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail("input check failed");
+    if (hb & 1) return fail("positions must be finite with |x| < 2^60");
+    if (hb & 2) return fail("masses must be finite and > 0");
+  }
 
   // Root cube (the host's rule on the device's bounding box).
   const int nbb = (int)std::min<int64_t>(1024, blocks(n));

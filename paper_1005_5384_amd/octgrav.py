@@ -51,7 +51,9 @@ EXPORTED = ["octgrav_build_tree", "octgrav_build_tree_ex", "octgrav_forces", "oc
             "octgrav_last_timings", "octgrav_mlp_create", "octgrav_mlp_free",
             "octgrav_mlp_set_stream", "octgrav_mlp_set_params", "octgrav_mlp_get_params",
             "octgrav_mlp_forward", "octgrav_mlp_loss_grad", "octgrav_mlp_adam", "octgrav_set_mac",
-            "octgrav_mac_stats", "octgrav_mac_trace"]
+            "octgrav_mac_stats", "octgrav_mac_trace", "octgrav_sim_create", "octgrav_sim_free",
+            "octgrav_sim_set_stream", "octgrav_sim_run", "octgrav_sim_energy", "octgrav_sim_state",
+            "octgrav_sim_timings"]
 
 N_PARAMS = 12 * 64 + 64 + 64 * 64 + 64 + 64 + 1  # 5057
 
@@ -103,6 +105,15 @@ def lib():
         L.octgrav_set_mac.argtypes = [vp, vp, f32, f32, f32, f32]
         L.octgrav_mac_stats.argtypes = [vp, vp]
         L.octgrav_mac_trace.argtypes = [vp, f32, vp, vp, vp, i64, C.POINTER(i64), vp]
+        L.octgrav_sim_create.restype = vp
+        L.octgrav_sim_create.argtypes = [vp, vp, vp, i64, i32, i32]
+        L.octgrav_sim_free.argtypes = [vp]
+        L.octgrav_sim_free.restype = None
+        L.octgrav_sim_set_stream.argtypes = [vp, vp]
+        L.octgrav_sim_run.argtypes = [vp, f32, f32, f32, i32]
+        L.octgrav_sim_energy.argtypes = [vp, vp]
+        L.octgrav_sim_state.argtypes = [vp, vp, vp, vp]
+        L.octgrav_sim_timings.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -350,3 +361,57 @@ class Mlp:
         self._bind_stream()
         _check(lib().octgrav_mlp_adam(self._h, float(lr), float(beta1), float(beta2), float(eps),
                                       int(step)))
+
+
+class Sim:
+    """A particle system on the device advanced with kick-drift-kick leapfrog,
+    the tree rebuilt on the GPU every step."""
+
+    def __init__(self, pos, vel, mass, n_leaf=16, n_group=64):
+        pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+        vel = np.ascontiguousarray(vel, dtype=np.float32).reshape(-1, 3)
+        mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
+        self.n = pos.shape[0]
+        if vel.shape[0] != self.n or mass.shape[0] != self.n:
+            raise ValueError("pos, vel and mass disagree on n")
+        h = lib().octgrav_sim_create(_ptr(pos), _ptr(vel), _ptr(mass), self.n, int(n_leaf),
+                                     int(n_group))
+        if not h:
+            raise OctgravError(EINVAL, last_error())
+        self._h = C.c_void_p(h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.octgrav_sim_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _bind_stream(self):
+        import torch
+        _check(lib().octgrav_sim_set_stream(self._h,
+                                            C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def run(self, theta, eps, dt, steps):
+        self._bind_stream()
+        _check(lib().octgrav_sim_run(self._h, float(theta), float(eps), float(dt), int(steps)))
+
+    def energy(self):
+        """dict(K, W, E, P=[px, py, pz]) in FP64."""
+        out = np.zeros(6)
+        self._bind_stream()
+        _check(lib().octgrav_sim_energy(self._h, _ptr(out)))
+        return dict(K=out[0], W=out[1], E=out[2], P=out[3:6].copy())
+
+    def state(self):
+        pos = np.zeros((self.n, 3), np.float32)
+        vel = np.zeros((self.n, 3), np.float32)
+        acc = np.zeros((self.n, 3), np.float32)
+        _check(lib().octgrav_sim_state(self._h, _ptr(pos), _ptr(vel), _ptr(acc)))
+        return pos, vel, acc
+
+    def timings(self):
+        out = np.zeros(3)
+        _check(lib().octgrav_sim_timings(self._h, _ptr(out)))
+        return dict(step_ms=out[0], build_ms=out[1], forces_ms=out[2])

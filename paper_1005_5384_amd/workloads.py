@@ -60,6 +60,27 @@ def plummer(n: int, seed: int, a: float = 1.0, rcut: float = PLUMMER_RCUT):
     return pos.astype(np.float32), np.full(n, 1.0 / n, dtype=np.float32)
 
 
+def plummer_with_velocities(n: int, seed: int, rcut: float = PLUMMER_RCUT):
+    """Plummer sphere (a = 1, G = 1, total mass 1) in equilibrium: radii as
+    `plummer`, isotropic speeds v = q v_esc(r), v_esc = sqrt(2) (1 + r^2)^-1/4,
+    with q drawn from g(q) ~ q^2 (1 - q^2)^(7/2) by rejection (Aarseth, Henon &
+    Wielen 1974).  Returns float32 (pos, vel, mass)."""
+    rng = _rng(seed)
+    r = plummer_radii(rng, n, 1.0, rcut)
+    pos = _isotropic(rng, r)
+    q = np.empty(n)
+    todo = np.arange(n)
+    while todo.size:
+        x = rng.uniform(0.0, 1.0, todo.size)
+        y = rng.uniform(0.0, 0.1, todo.size)
+        ok = y < x * x * (1.0 - x * x) ** 3.5
+        q[todo[ok]] = x[ok]
+        todo = todo[~ok]
+    v = q * np.sqrt(2.0) * (1.0 + r * r) ** -0.25
+    vel = _isotropic(rng, v)
+    return pos.astype(np.float32), vel.astype(np.float32), np.full(n, 1.0 / n, dtype=np.float32)
+
+
 def two_plummer(n: int, seed: int, separation: float):
     """Two equal Plummer spheres (a = 1) whose centres are `separation` apart on x."""
     rng = _rng(seed)

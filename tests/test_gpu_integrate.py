@@ -1,0 +1,67 @@
+"""The leapfrog integrator on the GPU (tree rebuilt on the device every
+step) against the FP64 direct-sum leapfrog oracle, and energy / momentum
+conservation with the tree at theta = 0.5."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1005_5384_amd import octgrav as og
+from paper_1005_5384_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def test_theta0_trajectory_matches_oracle():
+    _torch()
+    pos, vel, m = W.plummer_with_velocities(512, 11)
+    eps, dt, steps = 0.05, 1.0 / 256, 40
+    S = og.Sim(pos, vel, m, 8, 32)
+    S.run(0.0, eps, dt, 0)
+    e0 = S.energy()
+    S.run(0.0, eps, dt, steps)
+    p, v, a = S.state()
+    rp, rv, ren = oracle.leapfrog(pos, vel, m, eps, dt, steps)
+    assert np.abs(p - rp).max() < 2e-5 * max(1.0, np.abs(rp).max())
+    assert np.abs(v - rv).max() < 2e-5 * np.abs(rv).max()
+    np.testing.assert_allclose(e0["K"], ren[0, 0], rtol=1e-6)
+    np.testing.assert_allclose(e0["W"], ren[0, 1], rtol=1e-5)
+    e1 = S.energy()
+    np.testing.assert_allclose(e1["K"], ren[-1, 0], rtol=1e-4)
+    np.testing.assert_allclose(e1["W"], ren[-1, 1], rtol=1e-4)
+
+
+def test_energy_and_momentum_conserved_with_the_tree():
+    _torch()
+    pos, vel, m = W.plummer_with_velocities(8192, 12)
+    S = og.Sim(pos, vel, m, 16, 64)
+    S.run(0.5, 0.01, 1.0 / 256, 0)
+    e0 = S.energy()
+    assert abs(2 * e0["K"] / abs(e0["W"]) - 1) < 0.06
+    S.run(0.5, 0.01, 1.0 / 256, 128)
+    e1 = S.energy()
+    assert abs(e1["E"] - e0["E"]) < 2e-3 * abs(e0["E"]), (e0, e1)
+    scale = float(np.sum(m * np.linalg.norm(vel, axis=1)))
+    assert np.linalg.norm(e1["P"] - e0["P"]) < 1e-3 * scale
+    t = S.timings()
+    assert t["step_ms"] > 0 and t["build_ms"] > 0 and t["forces_ms"] > 0
+
+
+def test_sim_argument_checks():
+    _torch()
+    pos, vel, m = W.plummer_with_velocities(64, 13)
+    S = og.Sim(pos, vel, m)
+    with pytest.raises(og.OctgravError):
+        S.energy()  # no forces yet
+    with pytest.raises(og.OctgravError):
+        S.run(1.5, 0.01, 0.01, 1)
+    with pytest.raises(og.OctgravError):
+        S.run(0.5, 0.0, 0.01, 1)
+    vel[3, 2] = np.inf
+    with pytest.raises(og.OctgravError):
+        og.Sim(pos, vel, m)
