@@ -98,6 +98,27 @@ def _errs(out, ar, pr):
             "pot_med": float(np.median(ep)), "pot_max": float(ep.max())}
 
 
+def integration_rate(n, theta, eps, steps, dt=1.0 / 256):
+    """Kick-drift-kick steps of an equilibrium Plummer sphere of n particles
+    with the tree rebuilt on the GPU every step: the science rate (particles
+    advanced per second) and the energy change over the timed steps."""
+    from paper_1005_5384_amd import octgrav as og
+    from paper_1005_5384_amd import workloads as W
+    pos, vel, m = W.plummer_with_velocities(n, 102)
+    S = og.Sim(pos, vel, m, 16, 64)
+    S.run(theta, eps, dt, 1)  # first forces and one step
+    e0 = S.energy()
+    S.run(theta, eps, dt, steps)
+    e1 = S.energy()
+    t = S.timings()
+    return {"workload": f"equilibrium Plummer sphere (Aarseth-Henon-Wielen velocities), n={n}",
+            "theta": theta, "eps": eps, "dt": dt, "steps": steps,
+            "ms_per_step": t["step_ms"], "tree_build_ms": t["build_ms"], "forces_ms": t["forces_ms"],
+            "particles_per_s": n / (t["step_ms"] * 1e-3),
+            "energy_rel_change": abs(e1["E"] - e0["E"]) / abs(e0["E"]),
+            "virial_2K_over_W": 2 * e0["K"] / abs(e0["W"])}
+
+
 def W_sample(n, w):
     from paper_1005_5384_amd import workloads as W
     return W.sample_indices(n, w.get("sample", 4096), w.get("sample_seed", 4096))
@@ -179,6 +200,8 @@ def main():
                     help="acceptance criterion of the timed steps")
     ap.add_argument("--tau", type=float, default=4.21e-4,
                     help="tau_pair of --mac learned (band 0.4-0.8, budget 30 tau)")
+    ap.add_argument("--no-integration", action="store_true",
+                    help="skip the leapfrog science-rate measurement")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the bench: time a plain device copy of this many bytes "
                          "(the reference for scaling hardware byte counters)")
@@ -296,6 +319,9 @@ def main():
                               "budget": 30.0 * args.tau})
         out["mac_stats"] = T.mac_stats()
         T.set_mac(None)
+    if not args.no_integration and args.workload == "plummer1m":
+        log("bench: leapfrog science rate ...")
+        out["integration"] = integration_rate(n, theta, eps, args.steps)
     if not args.no_learned:
         log("bench: learned criterion vs theta at p99 1e-3 ...")
         out["learned_vs_theta"] = learned_vs_theta(T, w, args.steps)
