@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -120,6 +121,10 @@ struct octgrav_tree : DevAlloc {
   // Learned acceptance criterion: a private copy of the network's packed image.
   void* d_mlp = nullptr;
   bool learned = false;
+  // Handles rebuilt in place (time integration) take their device buffers
+  // from pools that the next rebuild reuses.
+  std::unique_ptr<SeqPool> pool;
+  std::unique_ptr<BuildPools> build_pools;
 
   ~octgrav_tree() {
     for (void* p : allocs) hipFree(p);
@@ -142,11 +147,13 @@ struct octgrav_tree : DevAlloc {
     if (!host_partial) return OCTGRAV_OK;
     const int64_t n = h.n, nc = h.n_cells();
     h.perm.resize(n);
+    h.topo.resize((size_t)nc * 4);
     h.geo.resize((size_t)nc * 4);
     h.mp.resize((size_t)nc * 12);
     h.mp64.resize((size_t)nc * 10);
     h.box.resize((size_t)nc * 6);
     if (hipMemcpy(h.perm.data(), dt.perm, (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(h.topo.data(), dt.topo, (size_t)nc * 16, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(h.geo.data(), darr.geo_host, (size_t)nc * 16, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(h.mp.data(), dt.mp, (size_t)nc * 48, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(h.mp64.data(), darr.mp64, (size_t)nc * 80, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -158,6 +165,11 @@ struct octgrav_tree : DevAlloc {
 
   int dalloc(void** p, size_t bytes) {
     if (alloc_fault()) return fail(OCTGRAV_ENOMEM, "device allocation failed (injected)");
+    if (pool) {
+      *p = pool->take(bytes);
+      if (!*p) return fail(OCTGRAV_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      return OCTGRAV_OK;
+    }
     if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) {
       (void)hipGetLastError();
       return fail(OCTGRAV_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
@@ -167,6 +179,7 @@ struct octgrav_tree : DevAlloc {
   }
 
   void dfree(void* p) {
+    if (pool) return;  // pool slots live until the handle is freed
     auto it = std::find(allocs.begin(), allocs.end(), p);
     if (it != allocs.end()) {
       hipFree(p);
@@ -240,6 +253,33 @@ struct octgrav_tree : DevAlloc {
     return alloc_walk_buffers();
   }
 
+  // Rebuilds the tree of device-resident positions and masses in place: the
+  // previous tree's buffers, events and evaluation stream are reused.
+  int rebuild_on_device(const float* pos, const float* mass, int64_t n, int n_leaf, int n_group) {
+    if (!pool) {
+      pool = std::make_unique<SeqPool>();
+      build_pools = std::make_unique<BuildPools>();
+    }
+    pool->rewind();
+    h = HostTree();
+    dt = DevTree{};
+    wb = WalkBufs{};
+    darr = DeviceArrays{};
+    d_diag_part = d_diag = nullptr;
+    have_diag = counts_valid = false;
+    slot_c = slot_l = 0;
+    d_mlp = nullptr;
+    learned = false;
+    dev = false;
+    std::string err;
+    if (build_device_tree(pos, mass, true, n, n_leaf, n_group, h, dt, darr, *this, stream, err,
+                          build_pools.get()) != 0)
+      return fail(err.find("must be") != std::string::npos ? OCTGRAV_EINVAL : OCTGRAV_EHIP,
+                  g_err.empty() ? err : g_err);
+    host_partial = true;
+    return alloc_walk_buffers();
+  }
+
   // Walk and list buffers, scratch, events and the evaluation stream (after
   // the tree arrays are on the device, from either build).
   int alloc_walk_buffers() {
@@ -284,11 +324,11 @@ struct octgrav_tree : DevAlloc {
     if ((rc = dalloc(&p, 4 * 8))) return rc;
     d_diag = (double*)p;
     for (hipEvent_t& e : ev)
-      if (hipEventCreate(&e) != hipSuccess) return fail(OCTGRAV_EHIP, "hipEventCreate failed");
+      if (!e && hipEventCreate(&e) != hipSuccess) return fail(OCTGRAV_EHIP, "hipEventCreate failed");
     for (hipEvent_t& e : bev)
-      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
         return fail(OCTGRAV_EHIP, "hipEventCreate failed");
-    if (hipStreamCreateWithFlags(&eval_stream, hipStreamNonBlocking) != hipSuccess)
+    if (!eval_stream && hipStreamCreateWithFlags(&eval_stream, hipStreamNonBlocking) != hipSuccess)
       return fail(OCTGRAV_EHIP, "hipStreamCreate failed");
     gwork.assign(ng + 1, nw);
     for (int64_t w = nw - 1; w >= 0; --w) gwork[h.work[2 * w]] = w;
@@ -458,6 +498,7 @@ int octgrav_set_stream(octgrav_tree* t, void* hip_stream) {
 int octgrav_tree_stats(const octgrav_tree* t, octgrav_stats* s) {
   if (!t || !s) return fail(OCTGRAV_EINVAL, "NULL argument");
   const HostTree& h = t->h;
+  if (int rc = const_cast<octgrav_tree*>(t)->fetch_host_arrays()) return rc;
   int64_t leaves = 0;
   for (int64_t c = 0; c < h.n_cells(); ++c) leaves += h.topo[4 * c + 1] == 0;
   s->n = h.n;
@@ -1015,27 +1056,17 @@ struct octgrav_sim {
   }
 
   // Tree of the current positions and the forces on them.
+  // The handle is rebuilt in place, so its device buffers carry over from
+  // one step to the next.
   int rebuild_and_force(double* t_build, double* t_force) {
     auto t0 = std::chrono::steady_clock::now();
-    if (tree) {
-      octgrav_free(tree);
-      tree = nullptr;
+    if (!tree) {
+      tree = new (std::nothrow) octgrav_tree;
+      if (!tree) return fail(OCTGRAV_ENOMEM, "out of host memory");
     }
-    octgrav_tree* t = new octgrav_tree;
-    t->stream = stream;
-    std::string err;
-    if (build_device_tree(pos, mass, true, n, n_leaf, n_group, t->h, t->dt, t->darr, *t, stream,
-                          err) != 0) {
-      std::string keep = g_err.empty() ? err : g_err;
-      delete t;
-      return fail(err.find("must be") != std::string::npos ? OCTGRAV_EINVAL : OCTGRAV_EHIP, keep);
-    }
-    t->host_partial = true;
-    if (int rc = t->alloc_walk_buffers()) {
-      delete t;
-      return rc;
-    }
-    tree = t;
+    tree->stream = stream;
+    have_forces = false;
+    if (int rc = tree->rebuild_on_device(pos, mass, n, n_leaf, n_group)) return rc;
     auto t1 = std::chrono::steady_clock::now();
     if (int rc = octgrav_forces_ex(tree, theta, eps, acc, pot, 0)) return rc;
     auto t2 = std::chrono::steady_clock::now();

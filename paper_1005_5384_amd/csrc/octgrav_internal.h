@@ -157,10 +157,30 @@ int launch_mlp_adam(float* P, float* m, float* v, const float* g, float lr, floa
 // The persistent arrays are allocated through DevAlloc (owned by the
 // caller); DeviceArrays receives the FP64 boxes / moments, the unsigned
 // boundary image and the depths, which stay on the device.  Fills h with the
-// scalars and the small host arrays (depth, topo, groups, work).
+// scalars and the small host arrays (depth, groups, work); the topology stays
+// on the device with the rest.
 struct DevAlloc {
   virtual int alloc(void** p, size_t bytes) = 0;
   virtual ~DevAlloc() = default;
+};
+// Device buffers handed out in request order and kept for the next round of
+// requests in the same order: a repeated build (time integration) finds its
+// buffers in place and only a request that outgrows its slot reallocates it.
+struct SeqPool {
+  std::vector<void*> ptr;
+  std::vector<size_t> cap;
+  size_t next = 0;
+  void* take(size_t bytes);  // nullptr when the device allocation fails
+  void rewind() { next = 0; }
+  SeqPool() = default;
+  SeqPool(const SeqPool&) = delete;
+  SeqPool& operator=(const SeqPool&) = delete;
+  ~SeqPool();
+};
+// Scratch of the device build kept between builds: whole-build arrays,
+// per-level arrays (the same slots every level) and the cell arrays.
+struct BuildPools {
+  SeqPool outer, level, cells;
 };
 struct DeviceArrays {
   const double* box = nullptr;     // [nc * 6]
@@ -172,7 +192,8 @@ struct DeviceArrays {
 // (checked on the device).
 int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_device, int64_t n,
                       int n_leaf, int n_group, HostTree& h, DevTree& dt, DeviceArrays& out,
-                      DevAlloc& alloc, void* stream, std::string& err);
+                      DevAlloc& alloc, void* stream, std::string& err,
+                      BuildPools* pools = nullptr);
 
 // Leapfrog pieces: v += h a, x += dt v, and FP64 (1/2 sum m v^2, sum m v).
 int launch_kick(float* vel, const float* acc, int64_t n, float h, void* stream);

@@ -351,16 +351,21 @@ __global__ void work_kernel(const int32_t* __restrict__ nchunk, const int32_t* _
   for (int k = 0; k < nchunk[g]; ++k) work[pre[g] + k] = make_int2((int32_t)g, k * kChunk);
 }
 
-// Scratch allocations of one build, freed on every exit.
+// Scratch allocations of one build: fresh ones freed on every exit, or slots
+// of a pool kept for the next build.
 struct Scratch {
+  SeqPool* pool = nullptr;
   std::vector<void*> p;
+  explicit Scratch(SeqPool* sp) : pool(sp) {}
   ~Scratch() {
     for (void* q : p) hipFree(q);
   }
   template <typename T>
   T* get(int64_t count) {
+    const size_t bytes = std::max<size_t>((size_t)count * sizeof(T), 256);
+    if (pool) return static_cast<T*>(pool->take(bytes));
     void* q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>((size_t)count * sizeof(T), 256)) != hipSuccess) {
+    if (hipMalloc(&q, bytes) != hipSuccess) {
       (void)hipGetLastError();
       return nullptr;
     }
@@ -380,11 +385,47 @@ int exclusive_sum(const T* in, T* out, int64_t n, Scratch& S, hipStream_t s) {
 
 }  // namespace
 
+void* SeqPool::take(size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  if (next < ptr.size() && cap[next] >= bytes) return ptr[next++];
+  // Grown slots get a quarter of headroom so that the small changes of a
+  // tree from one step to the next do not reallocate them.
+  const size_t want = ((bytes + bytes / 4) + 255) & ~size_t(255);
+  void* q = nullptr;
+  if (next < ptr.size()) {
+    hipFree(ptr[next]);
+    ptr[next] = nullptr;
+    cap[next] = 0;
+  }
+  if (hipMalloc(&q, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (next == ptr.size()) {
+    ptr.push_back(q);
+    cap.push_back(want);
+  } else {
+    ptr[next] = q;
+    cap[next] = want;
+  }
+  return ptr[next++];
+}
+
+SeqPool::~SeqPool() {
+  for (void* q : ptr)
+    if (q) hipFree(q);
+}
+
 int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_device, int64_t n,
                       int n_leaf, int n_group, HostTree& h, DevTree& dt, DeviceArrays& out,
-                      DevAlloc& alloc, void* stream, std::string& err) {
+                      DevAlloc& alloc, void* stream, std::string& err, BuildPools* pools) {
   hipStream_t s = (hipStream_t)stream;
-  Scratch S;
+  if (pools) {
+    pools->outer.rewind();
+    pools->cells.rewind();
+  }
+  Scratch S(pools ? &pools->outer : nullptr);
+  Scratch CS(pools ? &pools->cells : nullptr);
   auto fail = [&](const char* what) {
     err = what;
     return -1;
@@ -466,8 +507,8 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   auto grow = [&](int64_t need) -> bool {
     if (need <= cap && C.first) return true;
     const int64_t nc2 = C.first ? std::max(need, cap + cap / 2) : need;
-    Cells D{S.get<int32_t>(nc2), S.get<int32_t>(nc2), S.get<int32_t>(nc2),
-            S.get<int32_t>(nc2), S.get<int32_t>(nc2), S.get<int32_t>(nc2)};
+    Cells D{CS.get<int32_t>(nc2), CS.get<int32_t>(nc2), CS.get<int32_t>(nc2),
+            CS.get<int32_t>(nc2), CS.get<int32_t>(nc2), CS.get<int32_t>(nc2)};
     if (!D.first || !D.n || !D.depth || !D.parent || !D.fc || !D.nc) return false;
     if (C.first) {
       int32_t* src[6] = {C.first, C.n, C.depth, C.parent, C.fc, C.nc};
@@ -490,7 +531,8 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   int64_t lbeg = 0, lend = 1;
   for (int L = 0; lbeg < lend; ++L) {
     const int64_t m = lend - lbeg;
-    Scratch LS;
+    if (pools) pools->level.rewind();  // the previous level's scratch is dead
+    Scratch LS(pools ? &pools->level : nullptr);
     int32_t* bd = LS.get<int32_t>(9 * m);
     int32_t* nkid = LS.get<int32_t>(m + 1);
     int32_t* pre = LS.get<int32_t>(m + 1);
@@ -511,7 +553,9 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
     lbeg = lend;
     lend += total;
     level_beg.push_back(lbeg);  // level L spans [level_beg[L], level_beg[L + 1])
-    if (hipStreamSynchronize(s) != hipSuccess) return fail("subdivision failed");
+    // Fresh level scratch is freed at the end of the iteration: let the level
+    // finish first (pool slots are reused in stream order instead).
+    if (!pools && hipStreamSynchronize(s) != hipSuccess) return fail("subdivision failed");
   }
   const int64_t nc = lend;
 
@@ -580,11 +624,9 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   // Host copies the rest of the library needs now (the remaining arrays are
   // fetched on export).
   h.depth.resize(nc);
-  h.topo.resize((size_t)nc * 4);
   h.groups.resize(ng);
   h.work.resize((size_t)nw * 2);
   if (hipMemcpyAsync(h.depth.data(), depth, (size_t)nc * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(h.topo.data(), topo, (size_t)nc * 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(h.groups.data(), groups, (size_t)ng * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(h.work.data(), work, (size_t)nw * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
