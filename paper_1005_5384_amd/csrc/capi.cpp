@@ -498,9 +498,11 @@ int octgrav_set_stream(octgrav_tree* t, void* hip_stream) {
 int octgrav_tree_stats(const octgrav_tree* t, octgrav_stats* s) {
   if (!t || !s) return fail(OCTGRAV_EINVAL, "NULL argument");
   const HostTree& h = t->h;
-  if (int rc = const_cast<octgrav_tree*>(t)->fetch_host_arrays()) return rc;
-  int64_t leaves = 0;
-  for (int64_t c = 0; c < h.n_cells(); ++c) leaves += h.topo[4 * c + 1] == 0;
+  int64_t leaves = h.n_leaves;
+  if (leaves < 0) {
+    leaves = 0;
+    for (int64_t c = 0; c < h.n_cells(); ++c) leaves += h.topo[4 * c + 1] == 0;
+  }
   s->n = h.n;
   s->n_cells = h.n_cells();
   s->n_leaves = leaves;

@@ -17,6 +17,7 @@ struct HostTree {
   double corner[3] = {0, 0, 0}, side = 1;   // root cube
   int max_depth = 0;
   int64_t max_level_cells = 0;
+  int64_t n_leaves = -1;         // counted by the device build (-1: count from topo)
   std::vector<int32_t> perm;     // [n] sorted position -> input index
   std::vector<float> part;       // [n*4] sorted x, y, z, m
   std::vector<int32_t> topo;     // [nc*4] first_child, n_child, first, n

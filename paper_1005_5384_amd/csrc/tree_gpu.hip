@@ -269,12 +269,15 @@ __global__ void images_kernel(Cells C, int64_t nc, const double* __restrict__ bo
                               const double* __restrict__ mp64, int4* __restrict__ topo,
                               float4* __restrict__ geo_host, float4* __restrict__ geo,
                               float4* __restrict__ wrec, float4* __restrict__ mp,
-                              float4* __restrict__ fcell) {
+                              float4* __restrict__ fcell, int32_t* __restrict__ n_leaves) {
 #pragma clang fp contract(off)
   const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (c >= nc) return;
   const int4 tp = make_int4(C.fc[c], C.nc[c], C.first[c], C.n[c]);
   topo[c] = tp;
+  const unsigned long long leafs = __ballot(tp.y == 0);
+  if (leafs && __lane_id() == __ffsll((unsigned long long)leafs) - 1)
+    atomicAdd(n_leaves, (int32_t)__popcll(leafs));
   const double* bx = box + 6 * c;
   double l = 0;
   float g[3];
@@ -583,7 +586,11 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
       !A((void**)&mp, (size_t)nc * 48) || !A((void**)&fcell, (size_t)nc * 32) ||
       !A((void**)&depth, (size_t)nc * 4))
     return fail("device allocation failed");
-  images_kernel<<<blocks(nc), kT, 0, s>>>(C, nc, box, mp64, topo, geo_host, geo, wrec, mp, fcell);
+  int32_t* nleaf = S.get<int32_t>(1);
+  if (!nleaf) return fail("device allocation failed");
+  if (hipMemsetAsync(nleaf, 0, 4, s) != hipSuccess) return fail("memset failed");
+  images_kernel<<<blocks(nc), kT, 0, s>>>(C, nc, box, mp64, topo, geo_host, geo, wrec, mp, fcell,
+                                          nleaf);
   if (hipMemcpyAsync(depth, C.depth, (size_t)nc * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail("copy failed");
 
@@ -626,11 +633,14 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   h.depth.resize(nc);
   h.groups.resize(ng);
   h.work.resize((size_t)nw * 2);
+  int32_t leaves = 0;
   if (hipMemcpyAsync(h.depth.data(), depth, (size_t)nc * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&leaves, nleaf, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(h.groups.data(), groups, (size_t)ng * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(h.work.data(), work, (size_t)nw * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail("host copies failed");
+  h.n_leaves = leaves;
 
   dt.part = reinterpret_cast<const float*>(part);
   dt.perm = perm;
