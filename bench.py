@@ -25,6 +25,7 @@ FLOP_PP, FLOP_PC = 38, 70  # the paper's per-interaction convention (Sec. 3.3)
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_eval_kernel_plummer1m_theta0.5_traffic.md")
+HWFLOPS_PROFILE = os.path.join(ROOT, "profiles", "walk_eval_kernel_plummer1m_theta0.5_hwflops.md")
 
 
 def source_digest(files):
@@ -40,16 +41,21 @@ def source_digest(files):
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the default kernel from the committed counter
+def recorded(path, key):
+    """A per-launch figure of the default kernel from a committed counter
     summary, if the kernel's code is still the one it was taken with."""
     import re
     try:
-        txt = open(TRAFFIC_PROFILE).read()
+        txt = open(path).read()
         d = json.loads(re.search(r"```json\n(.*?)```", txt, re.S).group(1))
-        return d["traffic_bytes"] if source_digest(d["sources"]) == d["source_sha256"] else None
+        return d[key] if source_digest(d["sources"]) == d["source_sha256"] else None
     except (OSError, AttributeError, KeyError, ValueError):
         return None
+
+
+def recorded_traffic():
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy)."""
+    return recorded(TRAFFIC_PROFILE, "traffic_bytes")
 
 
 def log(*a):
@@ -117,6 +123,32 @@ def integration_rate(n, theta, eps, steps, dt=1.0 / 256):
             "particles_per_s": n / (t["step_ms"] * 1e-3),
             "energy_rel_change": abs(e1["E"] - e0["E"]) / abs(e0["E"]),
             "virial_2K_over_W": 2 * e0["K"] / abs(e0["W"])}
+
+
+def list_spread(T, theta):
+    """Spread of the theta walk's per-group list lengths |C_g|, |L_g| and
+    source-particle counts n_pp(g), and of the algorithmic FLOPs per 32-target
+    work item (the unit a wave takes from the work counter)."""
+    c_off, c_ids, l_off, l_ids = T.lists(theta)
+    ex = T.export()
+    cnt = ex["topo"][:, 3].astype(np.int64)
+    gsize = cnt[ex["groups"]]
+    n_c = np.diff(c_off)
+    n_l = np.diff(l_off)
+    cs = np.concatenate([[0], np.cumsum(cnt[l_ids])])
+    n_pp = cs[l_off[1:]] - cs[l_off[:-1]]
+    items = (gsize + 31) // 32
+    g = np.repeat(np.arange(gsize.size), items)
+    k = np.arange(g.size) - np.repeat(np.cumsum(items) - items, items)
+    tgt = np.minimum(32, gsize[g] - 32 * k)
+    flops = tgt * (38.0 * n_pp[g] + 70.0 * n_c[g])
+    q = lambda a: {"min": float(a.min()), "median": float(np.median(a)),
+                   "p90": float(np.quantile(a, 0.9)), "p99": float(np.quantile(a, 0.99)),
+                   "max": float(a.max()), "mean": float(a.mean())}
+    return {"theta": theta, "groups": int(gsize.size), "group_size": q(gsize),
+            "cell_list": q(n_c), "leaf_list": q(n_l), "pp_sources": q(n_pp),
+            "work_items": int(g.size), "item_flops": q(flops),
+            "item_max_over_mean": float(flops.max() / flops.mean())}
 
 
 def W_sample(n, w):
@@ -200,6 +232,8 @@ def main():
                     help="acceptance criterion of the timed steps")
     ap.add_argument("--tau", type=float, default=4.21e-4,
                     help="tau_pair of --mac learned (band 0.4-0.8, budget 30 tau)")
+    ap.add_argument("--list-spread", action="store_true",
+                    help="report per-group list lengths and per-work-item FLOPs (on for clumps4m)")
     ap.add_argument("--no-integration", action="store_true",
                     help="skip the leapfrog science-rate measurement")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -305,6 +339,7 @@ def main():
                                                         and args.path is None and args.mac == "theta")
                                  else None),
                      "flops_per_launch": flops, "flop_convention": "38 per p-p, 70 per p-c"},
+        "hw_fp32": None,
         "path_frac_peak": path_tflops / PEAK_FP32_TFLOPS,
         "path_tflops": path_tflops,
         "interactions_per_s": (counts["n_pp"] + counts["n_pc"]) / (ms_step * 1e-3),
@@ -314,11 +349,24 @@ def main():
         "device_build_s": t_dev_build,
         "tree": T.stats,
     }
+    default_kernel = (args.workload == "plummer1m" and theta == 0.5 and args.path is None
+                      and args.mac == "theta")
+    hw = recorded(HWFLOPS_PROFILE, "hw_fp32_flops_per_launch") if default_kernel else None
+    if hw:
+        # Hardware-counted FP32 operations of the same kernel (FMA = 2, one per
+        # active lane) over this run's kernel time: the paper's convention
+        # counts more per interaction than the instructions execute.
+        out["hw_fp32"] = {"flops_per_launch": hw, "tflops": hw / eval_s / 1e12,
+                          "frac": hw / eval_s / 1e12 / PEAK_FP32_TFLOPS,
+                          "counters": "SQ_INSTS_VALU_FLOPS_FP32 + SQ_INSTS_VALU_FLOPS_FP32_TRANS"}
     if args.mac == "learned":
         out["config"].update({"tau_pair": args.tau, "theta_lo": 0.4, "theta_hi": 0.8,
                               "budget": 30.0 * args.tau})
         out["mac_stats"] = T.mac_stats()
         T.set_mac(None)
+    if args.list_spread or (args.workload == "clumps4m" and args.mac == "theta"):
+        log("bench: list-length spread ...")
+        out["list_spread"] = list_spread(T, theta)
     if not args.no_integration and args.workload == "plummer1m":
         log("bench: leapfrog science rate ...")
         out["integration"] = integration_rate(n, theta, eps, args.steps)
