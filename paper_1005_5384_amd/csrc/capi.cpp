@@ -312,7 +312,8 @@ struct octgrav_tree : DevAlloc {
     while (cap < 2 * h.max_level_cells + 64) cap <<= 1;
     wb.gq_cap = cap;
     wb.gq_waves = fallback_waves();
-    while (wb.gq_waves > 8 && (int64_t)wb.gq_waves * cap * 4 > (int64_t(1) << 30)) wb.gq_waves >>= 1;
+    // At most 4 GiB of queues.
+    while (wb.gq_waves > 64 && (int64_t)wb.gq_waves * cap * 4 > (int64_t(1) << 32)) wb.gq_waves >>= 1;
     if ((rc = dalloc(&p, (size_t)wb.gq_waves * cap * 4))) return rc;
     wb.gq = (int32_t*)p;
     wb.lds_qcap = lds_queue_entries();

@@ -24,7 +24,7 @@ namespace {
 
 using namespace dev;
 
-constexpr int kFallbackWaves = 128;
+constexpr int kFallbackWaves = 2048;
 
 // One wave walks group g.  MODE 0 counts, MODE 1 writes at the offsets,
 // MODE 2 counts and writes into the group's fixed-size slots (entries past

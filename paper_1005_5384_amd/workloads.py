@@ -169,6 +169,57 @@ def galaxy_mix(n: int, seed: int, n_clumps: int = 256):
     return pos.astype(np.float32), np.full(n, 1.0 / n, dtype=np.float32)
 
 
+def _hernquist_radii(rng: np.random.Generator, n: int, a: float, rcut: float) -> np.ndarray:
+    """Hernquist radii: M(<r)/M = (r / (r + a))^2, so r = a sqrt(X) / (1 - sqrt(X))."""
+    def inv(x):
+        s = np.sqrt(x)
+        with np.errstate(divide="ignore"):
+            return a * s / (1.0 - s)
+    return _radii(rng, n, inv, rcut)
+
+
+def _exp_disc(rng: np.random.Generator, m: int, rd: float, zd: float) -> np.ndarray:
+    """Exponential disc: R ~ Gamma(2, rd) cut at 10 rd, sech^2 vertical profile
+    z = zd atanh(2U - 1) cut at 10 zd, uniform azimuth."""
+    R = np.empty(m)
+    todo = np.arange(m)
+    while todo.size:
+        v = rng.gamma(2.0, rd, todo.size)
+        ok = v <= 10 * rd
+        R[todo[ok]] = v[ok]
+        todo = todo[~ok]
+    z = np.empty(m)
+    todo = np.arange(m)
+    while todo.size:
+        u = rng.uniform(0.0, 1.0, todo.size)
+        with np.errstate(divide="ignore"):
+            v = zd * np.arctanh(2.0 * u - 1.0)
+        ok = np.isfinite(v) & (np.abs(v) <= 10 * zd)
+        z[todo[ok]] = v[ok]
+        todo = todo[~ok]
+    ph = rng.uniform(0.0, 2.0 * np.pi, m)
+    return np.stack([R * np.cos(ph), R * np.sin(ph), z], axis=1)
+
+
+# Component fractions of the Milky-Way-like stand-in: bulge : disc : halo =
+# 1 : 1 : 4 by mass, the proportions of the paper's galaxy model (Sec. 3).
+MW_FRACTIONS = (1.0 / 6.0, 1.0 / 6.0, 4.0 / 6.0)
+
+
+def milky_way(n: int, seed: int):
+    """Milky-Way-like stand-in with equal-mass particles: a Hernquist bulge
+    (a = 0.1, cut 30a), an exponential disc (R_d = 0.3, z_d = 0.03) and a
+    Hernquist halo (a = 1, cut 100a) holding 1/6, 1/6 and 4/6 of the particles
+    (largest-remainder counts)."""
+    rng = _rng(seed)
+    nb, nd, nh = _largest_remainder(np.array(MW_FRACTIONS), n)
+    bulge = _isotropic(rng, _hernquist_radii(rng, int(nb), 0.1, 3.0))
+    disc = _exp_disc(rng, int(nd), 0.3, 0.03)
+    halo = _isotropic(rng, _hernquist_radii(rng, int(nh), 1.0, 100.0))
+    pos = np.concatenate([bulge, disc, halo])
+    return pos.astype(np.float32), np.full(n, 1.0 / n, dtype=np.float32)
+
+
 def sample_indices(n: int, k: int, seed: int) -> np.ndarray:
     """k distinct particle indices drawn without replacement (sorted, int64)."""
     rng = _rng(seed)
@@ -185,6 +236,8 @@ WORKLOADS = {
                      thetas=(0.5,), sample=4096, sample_seed=4096),
     "galaxy16m": dict(gen="galaxy_mix", n=1 << 24, seed=108, eps=5e-4, n_leaf=32,
                       thetas=(0.5,), sample=4096, sample_seed=4096),
+    "milkyway1m": dict(gen="milky_way", n=1 << 20, seed=109, eps=1e-3, n_leaf=16,
+                       thetas=(0.5,), sample=4096, sample_seed=4096),
 }
 
 
@@ -212,5 +265,6 @@ def make(name: str, n: int | None = None):
     """Positions [n,3] f32 and masses [n] f32 of a named workload."""
     w = WORKLOADS[name]
     n = w["n"] if n is None else n
-    gen = {"plummer": plummer, "plummer_clumps": plummer_clumps, "galaxy_mix": galaxy_mix}[w["gen"]]
+    gen = {"plummer": plummer, "plummer_clumps": plummer_clumps, "galaxy_mix": galaxy_mix,
+           "milky_way": milky_way}[w["gen"]]
     return gen(n, w["seed"])
