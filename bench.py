@@ -156,7 +156,7 @@ def W_sample(n, w):
     return W.sample_indices(n, w.get("sample", 4096), w.get("sample_seed", 4096))
 
 
-def learned_vs_theta(T, w, steps, band=(0.4, 0.8), beta=30.0, target=1e-3):
+def learned_vs_theta(T, w, steps, band=(0.4, 0.8), beta=30.0, target=1e-3, params=None):
     """The learned acceptance criterion against the opening angle at equal
     p99 relative force error (against the GPU direct sum on the 4096-particle
     sample): theta* by bisection, then tau_pair (budget = beta * tau_pair) by
@@ -188,7 +188,7 @@ def learned_vs_theta(T, w, steps, band=(0.4, 0.8), beta=30.0, target=1e-3):
     t_th = timed(th)
     c_th = T.last_counts()
     log(f"bench: theta* {th:.4f} p99 {e_th:.3e} {t_th * 1e3:.3f} ms")
-    net = og.Mlp(L.load_params())
+    net = og.Mlp(L.load_params() if params is None else L.load_params(params))
 
     def p99_tau(lt):
         T.set_mac(net, band[0], band[1], 10.0 ** lt, beta * 10.0 ** lt)
@@ -232,6 +232,9 @@ def main():
                     help="acceptance criterion of the timed steps")
     ap.add_argument("--tau", type=float, default=4.21e-4,
                     help="tau_pair of --mac learned (band 0.4-0.8, budget 30 tau)")
+    ap.add_argument("--params", default=None,
+                    help="network parameters of the learned criterion (.npy, 5057 float32; "
+                         "default: the shipped network)")
     ap.add_argument("--list-spread", action="store_true",
                     help="report per-group list lengths and per-work-item FLOPs (on for clumps4m)")
     ap.add_argument("--no-integration", action="store_true",
@@ -287,7 +290,7 @@ def main():
     theta, eps = args.theta, w["eps"]
     if args.mac == "learned":
         from paper_1005_5384_amd import learned as L
-        net = og.Mlp(L.load_params())
+        net = og.Mlp(L.load_params() if args.params is None else L.load_params(args.params))
         T.set_mac(net, 0.4, 0.8, args.tau, 30.0 * args.tau)
 
     for _ in range(args.warmup):
@@ -372,7 +375,7 @@ def main():
         out["integration"] = integration_rate(n, theta, eps, args.steps)
     if not args.no_learned:
         log("bench: learned criterion vs theta at p99 1e-3 ...")
-        out["learned_vs_theta"] = learned_vs_theta(T, w, args.steps)
+        out["learned_vs_theta"] = learned_vs_theta(T, w, args.steps, params=args.params)
     # FP32 plain accumulation (no compensation) on the same call, for comparison
     plain = None
     if args.mac == "theta":

@@ -79,12 +79,34 @@ def train(x, y, epochs=30, batch=4096, lr=1e-3, tau=PINBALL_TAU, seed=0, params=
     return m
 
 
-def training_data(stride=1, log=None):
+def merger_snapshots(n, seed, separation, impact, dt, every, count, theta, eps=W.TRAINING_EPS):
+    """Positions and masses of a two-Plummer merger run on the GPU (the
+    library's leapfrog, tree rebuilt every step): the initial conditions and
+    then a snapshot every `every` steps, `count` in all."""
+    pos, vel, m = W.plummer_pair_orbit(n, seed, separation, impact)
+    S = og.Sim(pos, vel, m, 16, 64)
+    S.run(theta, eps, dt, 0)
+    out = [(pos, m)]
+    for _ in range(1, count):
+        S.run(theta, eps, dt, every)
+        out.append((S.state()[0], m))
+    S.close()
+    return out
+
+
+def training_data(stride=1, log=None, merger=False):
+    """Band pairs of the static training sets and, with `merger`, of the
+    merger run's snapshots."""
     import torch
-    xs, ys = [], []
-    for k in range(len(W.TRAINING_SETS)):
+    sets = [W.make_training(k) for k in range(len(W.TRAINING_SETS))]
+    if merger:
         t0 = time.time()
-        pos, mass = W.make_training(k)
+        sets += merger_snapshots(**W.MERGER_SET)
+        if log:
+            log(f"merger run: {W.MERGER_SET['count']} snapshots in {time.time() - t0:.1f} s")
+    xs, ys = [], []
+    for k, (pos, mass) in enumerate(sets):
+        t0 = time.time()
         x, y = collect(pos, mass, W.TRAINING_EPS, stride=stride)
         xs.append(x)
         ys.append(y)
@@ -133,9 +155,11 @@ def main():
     tr.add_argument("--epochs", type=int, default=30)
     tr.add_argument("--stride", type=int, default=1)
     tr.add_argument("--seed", type=int, default=0)
+    tr.add_argument("--merger", action="store_true",
+                    help="add the snapshots of a two-Plummer merger run to the static sets")
     a = ap.parse_args()
     if a.cmd == "train":
-        x, y = training_data(a.stride, log=lambda s: print(s, flush=True))
+        x, y = training_data(a.stride, log=lambda s: print(s, flush=True), merger=a.merger)
         t0 = time.time()
         m = train(x, y, epochs=a.epochs, seed=a.seed, log=lambda s: print(s, flush=True))
         print(f"trained on {x.shape[0]} pairs in {time.time() - t0:.1f} s", flush=True)

@@ -60,12 +60,11 @@ def plummer(n: int, seed: int, a: float = 1.0, rcut: float = PLUMMER_RCUT):
     return pos.astype(np.float32), np.full(n, 1.0 / n, dtype=np.float32)
 
 
-def plummer_with_velocities(n: int, seed: int, rcut: float = PLUMMER_RCUT):
-    """Plummer sphere (a = 1, G = 1, total mass 1) in equilibrium: radii as
-    `plummer`, isotropic speeds v = q v_esc(r), v_esc = sqrt(2) (1 + r^2)^-1/4,
-    with q drawn from g(q) ~ q^2 (1 - q^2)^(7/2) by rejection (Aarseth, Henon &
-    Wielen 1974).  Returns float32 (pos, vel, mass)."""
-    rng = _rng(seed)
+def _plummer_phase(rng: np.random.Generator, n: int, rcut: float):
+    """FP64 positions and velocities of a Plummer sphere (a = 1, G = 1, total
+    mass 1) in equilibrium: radii as `plummer`, isotropic speeds
+    v = q v_esc(r), v_esc = sqrt(2) (1 + r^2)^-1/4, with q drawn from
+    g(q) ~ q^2 (1 - q^2)^(7/2) by rejection (Aarseth, Henon & Wielen 1974)."""
     r = plummer_radii(rng, n, 1.0, rcut)
     pos = _isotropic(rng, r)
     q = np.empty(n)
@@ -77,7 +76,39 @@ def plummer_with_velocities(n: int, seed: int, rcut: float = PLUMMER_RCUT):
         q[todo[ok]] = x[ok]
         todo = todo[~ok]
     v = q * np.sqrt(2.0) * (1.0 + r * r) ** -0.25
-    vel = _isotropic(rng, v)
+    return pos, _isotropic(rng, v)
+
+
+def plummer_with_velocities(n: int, seed: int, rcut: float = PLUMMER_RCUT):
+    """Plummer sphere (a = 1, G = 1, total mass 1) in equilibrium (see
+    `_plummer_phase`).  Returns float32 (pos, vel, mass)."""
+    pos, vel = _plummer_phase(_rng(seed), n, rcut)
+    return pos.astype(np.float32), vel.astype(np.float32), np.full(n, 1.0 / n, dtype=np.float32)
+
+
+def plummer_pair_orbit(n: int, seed: int, separation: float = 8.0, impact: float = 1.0,
+                       rcut: float = PLUMMER_RCUT):
+    """Initial conditions of a two-Plummer merger: two equilibrium spheres
+    (a = 1, half the particles and about half the mass each, internal speeds
+    scaled by sqrt(1/2) for that mass) whose centres are (separation, impact,
+    0) apart and approach along x at the parabolic relative speed
+    sqrt(2 G M_tot / r0), M_tot = 1.  The centre of mass is at rest at the
+    origin.  Returns float32 (pos, vel, mass)."""
+    rng = _rng(seed)
+    h = n // 2
+    pa, va = _plummer_phase(rng, h, rcut)
+    pb, vb = _plummer_phase(rng, n - h, rcut)
+    va *= np.sqrt(0.5)
+    vb *= np.sqrt(0.5)
+    r0 = np.array([separation, impact, 0.0])
+    v = np.sqrt(2.0 / np.linalg.norm(r0))
+    fa, fb = (n - h) / n, h / n  # each centre's share of the relative vector
+    pa += fa * r0
+    pb -= fb * r0
+    va[:, 0] -= fa * v
+    vb[:, 0] += fb * v
+    pos = np.concatenate([pa, pb])
+    vel = np.concatenate([va, vb])
     return pos.astype(np.float32), vel.astype(np.float32), np.full(n, 1.0 / n, dtype=np.float32)
 
 
@@ -251,6 +282,13 @@ TRAINING_SETS = (
     dict(gen="two_plummer", n=1 << 18, seed=107, separation=8.0),
 )
 TRAINING_EPS = 1e-3
+
+# Snapshots of a dynamic two-Plummer merger (the library's leapfrog, tree
+# rebuilt on the GPU every step) join the static sets: 2^18 particles,
+# centres 8 apart with impact parameter 1 on a parabolic orbit, dt = 1/64,
+# a snapshot every 256 steps (4 time units), five snapshots from t = 0 to 16.
+MERGER_SET = dict(n=1 << 18, seed=110, separation=8.0, impact=1.0, dt=1.0 / 64, every=256,
+                  count=5, theta=0.5)
 
 
 def make_training(k: int):

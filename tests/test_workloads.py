@@ -44,3 +44,21 @@ def test_nearest_rank():
     assert nearest_rank(x, 0.2) == 1.0 and nearest_rank(x, 0.21) == 2.0
     y = np.arange(1, 101, dtype=float)
     assert nearest_rank(y, 0.99) == 99.0 and nearest_rank(y, 0.9) == 90.0
+
+
+def test_plummer_pair_orbit():
+    n = 20001
+    pos, vel, m = W.plummer_pair_orbit(n, 4, separation=8.0, impact=1.0)
+    h = n // 2
+    p, v = pos.astype(np.float64), vel.astype(np.float64)
+    mom = (m[:, None].astype(np.float64) * v).sum(0)
+    assert np.abs(mom).max() < 5e-3                      # centre of mass at rest (sampling noise)
+    ca, cb = p[:h].mean(0), p[h:].mean(0)
+    np.testing.assert_allclose(ca - cb, [8.0, 1.0, 0.0], atol=0.15)
+    va, vb = v[:h].mean(0), v[h:].mean(0)
+    vpar = np.sqrt(2.0 / np.hypot(8.0, 1.0))            # parabolic: relative kinetic = potential
+    np.testing.assert_allclose(va - vb, [-vpar, 0.0, 0.0], atol=0.01)
+    # internal speeds scaled by sqrt(1/2) for half the mass: half the mean squared speed
+    da = ((v[:h] - va) ** 2).sum(1).mean()
+    _, v1, _ = W.plummer_with_velocities(h, 4)
+    np.testing.assert_allclose(da, 0.5 * (v1.astype(np.float64) ** 2).sum(1).mean(), rtol=0.05)
