@@ -59,6 +59,22 @@ extern "C" {
 #define OCTGRAV_FUSED_BLOCK 8u
 #define OCTGRAV_FUSED_WAVE 16u
 
+/* Opening-test variant for octgrav_forces_ex / octgrav_lists_ex.  The
+ * default test (Sec. 2.2, the test-cell listing; the reading fixed here)
+ * measures d from the cell's boundary centre cb to the group's box and opens
+ * iff d2 == 0 or d2 theta^2 < l^2.  OCTGRAV_MAC_COM measures d from the cell's
+ * FP32 centre of mass instead and enlarges the size by the offset between
+ * the two centres (Barnes' offset criterion, a variant the paper's choice of
+ * centre leaves open): delta = sqrtf((dx*dx + dy*dy) + dz*dz) with
+ * d = com - cb, l' = l + theta * delta, open iff d2 == 0 or
+ * d2 theta^2 < l'^2, all in FP32 without contraction (sqrtf correctly
+ * rounded).  It runs on the fused wave path only (with a path flag other than
+ * OCTGRAV_FUSED_WAVE, or with a learned criterion set: OCTGRAV_EINVAL) and
+ * accepts theta in [0, 0.57]: there every cell holding a particle of the group
+ * is opened (its centre of mass lies in its tight box, within sqrt(3) l of the
+ * particle), so no particle meets itself through a multipole. */
+#define OCTGRAV_MAC_COM 32u
+
 typedef struct octgrav_tree octgrav_tree;
 
 typedef struct {
@@ -117,7 +133,7 @@ octgrav_tree* octgrav_build_tree_ex(const float* pos, const float* mass, int64_t
  *   pot    device, n FP32, caller's order (written), or NULL
  * Runs on the handle's stream and returns once the results are complete on it.
  * All paths evaluate the same lists; the default picks the fastest measured
- * one for theta (the fused block walk below 0.45, the fused wave walks above).
+ * one for theta (the fused block walk below 0.43, the fused wave walks above).
  */
 int octgrav_forces(octgrav_tree* t, float theta, float eps, float* acc, float* pot);
 

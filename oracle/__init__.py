@@ -42,6 +42,8 @@ def lib():
         L.orc_mac_open.argtypes = [_f32p, _f32p, _f32p, C.c_float]
         for f in (L.orc_lists, L.orc_lists_brute):
             f.argtypes = [vp, C.c_float, vp, vp, vp, vp, vp, vp]
+        L.orc_mac_open_com.argtypes = [_f32p, _f32p, _f32p, _f32p, C.c_float]
+        L.orc_lists_com.argtypes = [vp, C.c_float, _f32p, C.c_int, vp, vp, vp, vp, vp, vp]
         L.orc_forces.argtypes = [vp, C.c_float, C.c_float, vp, C.c_int64, _f64p, vp]
         L.orc_counts.argtypes = [vp, C.c_float, _i64p]
         L.orc_leapfrog.argtypes = [_f64p, _f64p, _f64p, C.c_int64, C.c_double, C.c_double,
@@ -107,6 +109,12 @@ def mac_open(gmin, gmax, geo, theta) -> bool:
                                    np.asarray(geo, np.float32), float(theta)))
 
 
+def mac_open_com(gmin, gmax, com, geo, theta) -> bool:
+    """The centre-of-mass offset opening test of one cell for one group box."""
+    f = lambda a: np.ascontiguousarray(a, np.float32)
+    return bool(lib().orc_mac_open_com(f(gmin), f(gmax), f(com), f(geo), float(theta)))
+
+
 class Tree:
     """The oracle's own octree (independent builder), with its FP64 moments."""
 
@@ -162,6 +170,13 @@ class Tree:
     def lists_brute(self, theta):
         """The same lists from their walk-free characterisation (slow)."""
         return self._lists(lib().orc_lists_brute, theta)
+
+    def lists_com(self, theta, com, brute=False):
+        """Lists under the centre-of-mass offset test; com [n_cells, 3] is the
+        FP32 centre of mass of every cell (the test's input)."""
+        com = np.ascontiguousarray(com, np.float32).reshape(self.n_cells, 3)
+        fn = lambda h, th, *a: lib().orc_lists_com(h, th, com, int(brute), *a)
+        return self._lists(fn, theta)
 
     def counts(self, theta):
         """[n_groups, 3]: |C_g|, |L_g|, source particles in L_g."""

@@ -337,6 +337,74 @@ int lists_impl(const Tree& t, float theta, walk_fn fn, int64_t* c_off, int32_t* 
   return 0;
 }
 
+// Offset variant of the opening test (Barnes' criterion with the boundary
+// side as the size; the paper's choice of centre leaves this open): d from the
+// cell's FP32 centre of mass com to the group box, the size enlarged by
+// theta times the offset delta = |com - cb|, all in FP32 without contraction
+// and a correctly rounded square root:
+//   delta = sqrt((dx*dx + dy*dy) + dz*dz), d = com - cb;  l' = l + theta*delta;
+//   open iff d2 == 0 or d2 * theta^2 < l'^2   (d2 as in mac_open, about com).
+bool mac_open_com(const float gmin[3], const float gmax[3], const float com[3], const float geo[4],
+                  float theta) {
+  float dx = com[0] - geo[0], dy = com[1] - geo[1], dz = com[2] - geo[2];
+  float px = dx * dx, py = dy * dy, pz = dz * dz;
+  float delta = std::sqrt((px + py) + pz);
+  float td = theta * delta;
+  float g[4] = {com[0], com[1], com[2], geo[3] + td};
+  return mac_open(gmin, gmax, g, theta * theta);
+}
+
+// The tree walk (as walk_group) and the walk-free characterisation (as
+// brute_group) under the offset test; com is [n_cells x 3] FP32.
+void walk_group_com(const Tree& t, int32_t gcell, float theta, const float* com,
+                    std::vector<int32_t>& C, std::vector<int32_t>& Lv) {
+  C.clear();
+  Lv.clear();
+  if (t.cells[0].n_child == 0) {
+    Lv.push_back(0);
+    return;
+  }
+  float gmin[3], gmax[3];
+  group_box(t, gcell, gmin, gmax);
+  std::vector<int32_t> stack{0};
+  while (!stack.empty()) {
+    const Cell& nc = t.cells[stack.back()];
+    stack.pop_back();
+    for (int k = 0; k < nc.n_child; ++k) {
+      int32_t c = nc.first_child + k;
+      if (mac_open_com(gmin, gmax, com + 3 * (int64_t)c, t.cells[c].geo, theta)) {
+        if (t.cells[c].n_child == 0)
+          Lv.push_back(c);
+        else
+          stack.push_back(c);
+      } else {
+        C.push_back(c);
+      }
+    }
+  }
+  std::sort(C.begin(), C.end());
+  std::sort(Lv.begin(), Lv.end());
+}
+
+void brute_group_com(const Tree& t, int32_t gcell, float theta, const float* com,
+                     std::vector<int32_t>& C, std::vector<int32_t>& Lv) {
+  C.clear();
+  Lv.clear();
+  float gmin[3], gmax[3];
+  group_box(t, gcell, gmin, gmax);
+  int nc = (int)t.cells.size();
+  std::vector<char> opened(nc);
+  for (int c = 0; c < nc; ++c)
+    opened[c] = (c == 0) ? 1 : mac_open_com(gmin, gmax, com + 3 * (int64_t)c, t.cells[c].geo, theta);
+  for (int c = 0; c < nc; ++c) {
+    bool anc = true;
+    for (int a = t.cells[c].parent; a >= 0; a = t.cells[a].parent) anc = anc && opened[a];
+    if (!anc) continue;
+    if (!opened[c]) C.push_back(c);
+    else if (t.cells[c].n_child == 0) Lv.push_back(c);
+  }
+}
+
 // FP64 evaluation of one group's lists for each of its particles (Sec. 2.3).
 void eval_group(const Tree& t, int32_t gcell, const std::vector<int32_t>& C,
                 const std::vector<int32_t>& Lv, double eps2, double* acc, double* pot) {
@@ -552,6 +620,42 @@ int orc_lists(const void* h, float theta, int64_t* c_off, int32_t* c_ids, int64_
 int orc_lists_brute(const void* h, float theta, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
                     int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
   return lists_impl(*(const Tree*)h, theta, brute_group, c_off, c_ids, l_off, l_ids, n_c, n_l);
+}
+
+// Single offset test (see mac_open_com): 1 = open.
+int orc_mac_open_com(const float* gmin, const float* gmax, const float* com, const float* geo,
+                     float theta) {
+  return mac_open_com(gmin, gmax, com, geo, theta) ? 1 : 0;
+}
+
+// Lists under the offset test (brute != 0: from the walk-free
+// characterisation); com is the FP32 centre of mass of every cell [nc x 3].
+int orc_lists_com(const void* h, float theta, const float* com, int brute, int64_t* c_off,
+                  int32_t* c_ids, int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
+  const Tree& t = *(const Tree*)h;
+  int64_t ng = (int64_t)t.groups.size();
+  std::vector<std::vector<int32_t>> C(ng), Lv(ng);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t g = 0; g < ng; ++g) {
+    if (brute)
+      brute_group_com(t, t.groups[g], theta, com, C[g], Lv[g]);
+    else
+      walk_group_com(t, t.groups[g], theta, com, C[g], Lv[g]);
+  }
+  int64_t sc = 0, sl = 0;
+  for (int64_t g = 0; g < ng; ++g) {
+    if (c_off) c_off[g] = sc;
+    if (l_off) l_off[g] = sl;
+    if (c_ids) std::copy(C[g].begin(), C[g].end(), c_ids + sc);
+    if (l_ids) std::copy(Lv[g].begin(), Lv[g].end(), l_ids + sl);
+    sc += (int64_t)C[g].size();
+    sl += (int64_t)Lv[g].size();
+  }
+  if (c_off) c_off[ng] = sc;
+  if (l_off) l_off[ng] = sl;
+  if (n_c) *n_c = sc;
+  if (n_l) *n_l = sl;
+  return 0;
 }
 
 // Same-tree forces: walk + FP64 evaluation for the particles of the selected

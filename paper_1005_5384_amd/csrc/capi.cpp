@@ -121,6 +121,10 @@ struct octgrav_tree : DevAlloc {
   // Learned acceptance criterion: a private copy of the network's packed image.
   void* d_mlp = nullptr;
   bool learned = false;
+  // Walk records of the centre-of-mass offset test, for the theta they were
+  // made for (made on first use, remade when theta changes).
+  float* d_wrec_com = nullptr;
+  float com_theta = -1.0f;
   // Handles rebuilt in place (time integration) take their device buffers
   // from pools that the next rebuild reuses.
   std::unique_ptr<SeqPool> pool;
@@ -270,6 +274,8 @@ struct octgrav_tree : DevAlloc {
     slot_c = slot_l = 0;
     d_mlp = nullptr;
     learned = false;
+    d_wrec_com = nullptr;
+    com_theta = -1.0f;
     dev = false;
     std::string err;
     if (build_device_tree(pos, mass, true, n, n_leaf, n_group, h, dt, darr, *this, stream, err,
@@ -541,17 +547,19 @@ int octgrav_export_tree(const octgrav_tree* t, const octgrav_tree_view* v) {
 
 enum class Path { TwoPass, FusedBlock, FusedWave };
 
-// Path of a call: an explicit flag, else the fastest measured for theta on
-// 2^20 Plummer spheres (ms at theta 0.3 / 0.4 / 0.45 / 0.5 / 0.75: fused wave
-// 13.8 / 6.7 / 3.6 / 2.6 / 1.03, fused block 11.0 / 5.4 / 4.0 / 3.1 / 1.6,
-// two-pass 12.0 / 5.6 / 4.4 / 3.3 / 1.5).  The wave variant's 4096-entry LDS
-// queues for small angles limit it to a few walks per CU, where the block
+// Path of a call: an explicit flag, else the fastest measured for theta
+// (2^20 Plummer, 4M clumps and 2^20 Milky-Way-like sets; ms at theta 0.38 /
+// 0.42 / 0.44 / 0.46, fused block: Plummer 6.3 / 5.1 / 4.7 / 3.8, clumps
+// 24.7 / 19.9 / 18.0 / 15.0, Milky Way 8.8 / 7.0 / 6.3 / 5.0; fused wave:
+// 7.8 / 6.3 / 4.1 / 3.2, 32.2 / 16.9 / 14.7 / 12.7, 9.6 / 6.3 / 5.1 / 3.9;
+// the two-pass path trails both).  Below 0.4 the wave variant needs its
+// 4096-entry LDS queues, which allow only a few walks per CU, where the block
 // variant shares one queue among four waves.
 static Path choose_path(uint32_t flags, float theta) {
   if (flags & OCTGRAV_TWO_PASS) return Path::TwoPass;
   if (flags & OCTGRAV_FUSED_BLOCK) return Path::FusedBlock;
   if (flags & OCTGRAV_FUSED_WAVE) return Path::FusedWave;
-  return theta < 0.45f ? Path::FusedBlock : Path::FusedWave;  // measured crossover
+  return theta < 0.43f ? Path::FusedBlock : Path::FusedWave;  // measured crossover
 }
 
 static int launch_fused(const octgrav_tree* t, Path p, float theta, float eps, bool plain,
@@ -560,6 +568,46 @@ static int launch_fused(const octgrav_tree* t, Path p, float theta, float eps, b
                ? launch_walk_eval(t->dt, t->wb, theta, eps, plain, do_eval, acc, pot, t->stream)
                : launch_walk_eval_block(t->dt, t->wb, theta, eps, plain, do_eval, acc, pot, t->stream);
   return rc ? rc : launch_totals(t->dt, t->wb, t->stream);
+}
+
+// While alive, the handle's walks read the offset test's records at theta
+// (the evaluation's arrays are unchanged).
+struct ComRecords {
+  octgrav_tree* t = nullptr;
+  const float* saved = nullptr;
+  int rc = OCTGRAV_OK;
+  ComRecords(octgrav_tree* tt, bool on, float theta) {
+    if (!on) return;
+    if (!tt->d_wrec_com) {
+      void* p = nullptr;
+      if ((rc = tt->dalloc(&p, (size_t)tt->dt.nc * 32))) return;
+      tt->d_wrec_com = (float*)p;
+      tt->com_theta = -1.0f;
+    }
+    if (tt->com_theta != theta) {
+      if (launch_com_records(tt->dt, theta, tt->d_wrec_com, tt->stream)) {
+        rc = fail(OCTGRAV_EHIP, "offset-test record launch failed");
+        return;
+      }
+      tt->com_theta = theta;
+    }
+    t = tt;
+    saved = tt->dt.wrec;
+    tt->dt.wrec = tt->d_wrec_com;
+  }
+  ~ComRecords() {
+    if (t) t->dt.wrec = saved;
+  }
+};
+
+// Argument rules of OCTGRAV_MAC_COM.
+static int check_com(const octgrav_tree* t, uint32_t flags, float theta) {
+  if (!(flags & OCTGRAV_MAC_COM)) return OCTGRAV_OK;
+  if (t->learned) return fail(OCTGRAV_EINVAL, "the offset test and the learned criterion exclude each other");
+  if (flags & (OCTGRAV_TWO_PASS | OCTGRAV_FUSED_BLOCK))
+    return fail(OCTGRAV_EINVAL, "the offset test runs on the fused wave path only");
+  if (!(theta <= 0.57f)) return fail(OCTGRAV_EINVAL, "the offset test takes theta in [0, 0.57]");
+  return OCTGRAV_OK;
 }
 
 static int check_theta(const octgrav_tree* t, float theta) {
@@ -582,7 +630,11 @@ int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float
     int64_t tot[8];
     if (t->learned && (flags & (OCTGRAV_TWO_PASS | OCTGRAV_FUSED_BLOCK)))
       return fail(OCTGRAV_EINVAL, "the learned criterion runs on the fused wave path only");
-    const Path path = t->learned ? Path::FusedWave : choose_path(flags, theta);
+    if (int rc = check_com(t, flags, theta)) return rc;
+    const bool com = flags & OCTGRAV_MAC_COM;
+    const Path path = (t->learned || com) ? Path::FusedWave : choose_path(flags, theta);
+    ComRecords cr(t, com, theta);
+    if (cr.rc) return cr.rc;
     for (int attempt = 0; attempt < 2; ++attempt) {
       if (timed) {
         for (int k = 0; k < 4; ++k) hipEventRecord(t->ev[k], t->stream);
@@ -663,11 +715,16 @@ int octgrav_lists_ex(octgrav_tree* t, float theta, uint32_t flags, int64_t* c_of
     int64_t tot[8];
     if (t->learned && (flags & (OCTGRAV_TWO_PASS | OCTGRAV_FUSED_BLOCK)))
       return fail(OCTGRAV_EINVAL, "the learned criterion runs on the fused wave path only");
+    if (int rc = check_com(t, flags, theta)) return rc;
+    const bool com = flags & OCTGRAV_MAC_COM;
+    ComRecords cr(t, com, theta);
+    if (cr.rc) return cr.rc;
     // Count walk and offsets give the sizes; the buffers are made to fit.
-    // (The learned criterion counts with the fused walk itself.)
+    // (The learned criterion and the offset test count with the fused walk.)
     t->wb.export_lists = 0;
-    if (t->learned ? launch_fused(t, Path::FusedWave, theta, 1.0f, false, false, nullptr, nullptr) != 0
-                   : launch_walk(t->dt, t->wb, theta, 0, t->stream) != 0)
+    const bool fused_count = t->learned || com;
+    if (fused_count ? launch_fused(t, Path::FusedWave, theta, 1.0f, false, false, nullptr, nullptr) != 0
+                    : launch_walk(t->dt, t->wb, theta, 0, t->stream) != 0)
       return fail(OCTGRAV_EHIP, "count walk launch failed");
     if (launch_scan(t->dt, t->wb, t->stream)) return fail(OCTGRAV_EHIP, "offsets launch failed");
     if (int rc = t->read_tot(tot)) return rc;
@@ -675,7 +732,7 @@ int octgrav_lists_ex(octgrav_tree* t, float theta, uint32_t flags, int64_t* c_of
     if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
     *n_c = tot[0];
     *n_l = tot[1];
-    const Path path = t->learned ? Path::FusedWave : choose_path(flags, theta);
+    const Path path = fused_count ? Path::FusedWave : choose_path(flags, theta);
     if (path == Path::TwoPass) {
       if (launch_walk(t->dt, t->wb, theta, 1, t->stream)) return fail(OCTGRAV_EHIP, "write walk launch failed");
     } else {

@@ -1,6 +1,7 @@
-// Support kernels of the learned acceptance criterion: FP32 compensated
-// direct summation (the accuracy reference of Sec. 3.1, and the label
-// normalization), and the features + labels of band candidates.
+// Support kernels of the acceptance criteria: FP32 compensated direct
+// summation (the accuracy reference of Sec. 3.1, and the learned criterion's
+// label normalization), the features + labels of band candidates, and the
+// walk records of the centre-of-mass offset opening test.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -135,7 +136,35 @@ __global__ __launch_bounds__(kThreads) void mac_label_kernel(DevTree T, WalkBufs
   }
 }
 
+// Walk records of the offset opening test at one theta: the boundary of
+// each record becomes (com, l + theta |com - cb|) with the leaf sign bit kept,
+// the topology is copied, so the walk kernels' own test (d2 == 0 or
+// d2 theta^2 < w^2) evaluates the offset criterion unchanged.
+__global__ void com_record_kernel(const float4* __restrict__ wrec, const float4* __restrict__ mp,
+                                  int64_t nc, float theta, float4* __restrict__ out) {
+#pragma clang fp contract(off)
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= nc) return;
+  const float4 g = wrec[2 * c];
+  const float4 m0 = mp[3 * c];
+  const float dx = m0.x - g.x, dy = m0.y - g.y, dz = m0.z - g.z;
+  const float px = dx * dx, py = dy * dy, pz = dz * dz;
+  const float delta = sqrtf((px + py) + pz);  // correctly rounded (HIP default)
+  const float td = theta * delta;
+  const float lp = fabsf(g.w) + td;
+  out[2 * c] = make_float4(m0.x, m0.y, m0.z, copysignf(lp, g.w));
+  out[2 * c + 1] = wrec[2 * c + 1];
+}
+
 }  // namespace
+
+int launch_com_records(const DevTree& T, float theta, float* out, void* stream) {
+  if (T.nc <= 0) return 0;
+  com_record_kernel<<<(T.nc + kThreads - 1) / kThreads, kThreads, 0, (hipStream_t)stream>>>(
+      reinterpret_cast<const float4*>(T.wrec), reinterpret_cast<const float4*>(T.mp), T.nc, theta,
+      reinterpret_cast<float4*>(out));
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 int launch_direct(const DevTree& T, const int32_t* targets, int64_t nt, float eps, float* acc,
                   float* pot, void* stream) {

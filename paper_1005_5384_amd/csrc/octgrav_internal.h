@@ -133,6 +133,9 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
                      bool do_eval, float* acc, float* pot, void* stream);
 int launch_walk_eval_block(const DevTree& T, const WalkBufs& B, float theta, float eps, bool plain,
                            bool do_eval, float* acc, float* pot, void* stream);
+// Walk records (nc x 32 B, the layout of DevTree::wrec) of the centre-of-mass
+// offset opening test at theta: boundary (com, l + theta |com - cb|), topology.
+int launch_com_records(const DevTree& T, float theta, float* out, void* stream);
 // FP32 compensated direct sum for targets (caller indices, device array, or
 // NULL = all); outputs in target order.
 int launch_direct(const DevTree& T, const int32_t* targets, int64_t nt, float eps, float* acc,

@@ -483,13 +483,16 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
   const float th2 = theta * theta, eps2 = eps * eps;
   fused_init_kernel<<<1, 64, 0, s>>>(B);
   // The breadth-first FIFO holds about two tree levels of the group's walk,
-  // which grows like theta^-3: 1024 entries cover theta >= 0.45 on Plummer
-  // spheres of 2^20 (peak ~740 at 0.5), 4096 the smaller angles.  Tiers:
-  // 1024-entry LDS queues (theta >= 0.45 and the learned criterion; 16, or
-  // 12 with the network, waves per CU), then the overflows with 4096-entry
-  // LDS queues (one wave per block), then global-memory queues.
+  // which grows like theta^-3: 1024 entries hold most walks at theta >= 0.4 on
+  // 2^20-particle sets (peak ~740 at 0.5 on a Plummer sphere), 4096 the
+  // smaller angles.  Tiers: 1024-entry LDS queues (theta >= 0.4 and the
+  // learned criterion; 16, or 12 with the network, waves per CU), then the
+  // overflows with 4096-entry LDS queues (one wave per block), then
+  // global-memory queues.  Below 0.4 so many walks overflow the first tier
+  // that starting with the 4096-entry queues is faster (2^20 Plummer at
+  // 0.35: 9.6 instead of 35 ms).
   const bool learned = B.mlp != nullptr;
-  const bool wide = theta < 0.45f && !learned;
+  const bool wide = theta < 0.40f && !learned;
   auto go = [&](auto plain_tag, auto learned_tag) {
     constexpr bool P = decltype(plain_tag)::value, L = decltype(learned_tag)::value;
     if (wide) {

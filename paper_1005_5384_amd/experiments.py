@@ -1,11 +1,14 @@
 """Experiments around the force path (the paper's Sec. 3 and its parameter
 choices in Sec. 2): a sweep of the leaf and group capacities, including the
-per-particle walk (groups of one particle), and the force error against the
+per-particle walk (groups of one particle); the force error against the
 direct sum as a function of the opening angle and N on the Milky-Way-like
-stand-in of the paper's galaxy model. Every configuration prints one JSON line.
+stand-in of the paper's galaxy model; and the boundary-centre opening test
+against the centre-of-mass offset variant at equal error. Every
+configuration prints one JSON line.
 
     python -m paper_1005_5384_amd.experiments sweep [--workload plummer1m]
     python -m paper_1005_5384_amd.experiments errors
+    python -m paper_1005_5384_amd.experiments mac [--workload plummer1m]
 
 Errors are |a - a_ref| / |a_ref| (Sec. 3.1) on 4096 seeded sampled particles,
 a_ref from the library's compensated FP32 direct sum; percentiles are nearest
@@ -125,15 +128,67 @@ def error_curves(ns=(1 << 16, 1 << 18, 1 << 20, 1 << 22),
     return rows
 
 
+def mac_variants(workload="plummer1m", targets=(2.5e-4, 5e-4, 1e-3), steps=5, out=sys.stdout):
+    """The boundary-centre opening test against the centre-of-mass offset
+    test at equal p99 error: theta bisected for each (the offset test within
+    its range, theta <= 0.57), then both timed on the fused wave path (the
+    offset test's path) so that only the criterion differs."""
+    import torch
+    from .learned import bisect
+    w = W.WORKLOADS[workload]
+    pos, m = W.make(workload)
+    n, eps = pos.shape[0], w["eps"]
+    T = og.Tree(pos, m, w["n_leaf"], 64, device_build=True)
+    smp = torch.as_tensor(W.sample_indices(n, 4096, 4096), device="cuda")
+    ref, _ = T.direct(eps, smp)
+
+    def p99(theta, com):
+        acc, _ = T.forces(theta, eps, with_pot=False, com=com)
+        return _errors(acc[smp], ref)["p99"]
+
+    rows = []
+    for tgt in targets:
+        r = {"experiment": "mac_variants", "workload": workload, "n": n, "target_p99": tgt}
+        for name, com, hi in (("boundary", False, 1.0), ("com_offset", True, 0.57)):
+            th, e = bisect(lambda x: p99(x, com), 0.1, hi, tgt, increasing=True)
+            ms, c, _ = _timed_mac(T, th, eps, steps, com)
+            r[name] = {"theta": th, "p99": e, "ms": ms, "pc_per_particle": c["n_pc"] / n,
+                       "pp_per_particle": c["n_pp"] / n}
+        r["offset_speedup"] = r["boundary"]["ms"] / r["com_offset"]["ms"]
+        print(json.dumps(r), file=out, flush=True)
+        rows.append(r)
+    T.close()
+    return rows
+
+
+def _timed_mac(T, theta, eps, steps, com):
+    import torch
+    acc = torch.empty((T.n, 3), dtype=torch.float32, device="cuda")
+    path = "fused_wave"
+    T.forces(theta, eps, acc=acc, with_pot=False, com=com, path=path)
+    ms = []
+    for _ in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        T.forces(theta, eps, acc=acc, with_pot=False, com=com, path=path)
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    return float(np.median(ms)), T.last_counts(), acc
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("what", choices=["sweep", "errors"])
+    ap.add_argument("what", choices=["sweep", "errors", "mac"])
     ap.add_argument("--workload", default="plummer1m")
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--steps", type=int, default=5)
     a = ap.parse_args(argv)
     if a.what == "sweep":
         leaf_group_sweep(a.workload, a.theta, steps=a.steps)
+    elif a.what == "mac":
+        mac_variants(a.workload, steps=a.steps)
     else:
         error_curves(steps=a.steps)
 

@@ -22,6 +22,7 @@ TIMED = 2
 TWO_PASS = 4
 FUSED_BLOCK = 8
 FUSED_WAVE = 16
+MAC_COM = 32  # centre-of-mass offset opening test (fused wave path, theta <= 0.57)
 PATHS = {None: 0, "two_pass": TWO_PASS, "fused_block": FUSED_BLOCK, "fused_wave": FUSED_WAVE}
 
 _lib = None
@@ -163,8 +164,9 @@ class Tree:
         _check(lib().octgrav_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
     def forces(self, theta, eps, acc=None, pot=None, plain=False, timed=False, with_pot=True,
-               two_pass=False, path=None):
-        """(acc [n,3], pot [n]) as float32 torch tensors on the current device."""
+               two_pass=False, path=None, com=False):
+        """(acc [n,3], pot [n]) as float32 torch tensors on the current device;
+        com=True selects the centre-of-mass offset opening test."""
         import torch
         if acc is None:
             acc = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
@@ -177,16 +179,17 @@ class Tree:
             raise ValueError("acc must hold n*3 and pot n elements")
         self._bind_stream()
         flags = (PLAIN_SUM if plain else 0) | (TIMED if timed else 0) | (TWO_PASS if two_pass else 0)
-        flags |= PATHS[path]
+        flags |= PATHS[path] | (MAC_COM if com else 0)
         _check(lib().octgrav_forces_ex(self._h, float(theta), float(eps), C.c_void_p(acc.data_ptr()),
                                        None if pot is None else C.c_void_p(pot.data_ptr()), flags))
         return acc, pot
 
-    def lists(self, theta, two_pass=False, path=None):
+    def lists(self, theta, two_pass=False, path=None, com=False):
         """(c_off, c_ids, l_off, l_ids) numpy CSR lists built by the GPU walk of
-        the selected path (default: the force path's default for theta)."""
+        the selected path (default: the force path's default for theta) and
+        opening test (com=True: the centre-of-mass offset test)."""
         self._bind_stream()
-        fl = (TWO_PASS if two_pass else 0) | PATHS[path]
+        fl = (TWO_PASS if two_pass else 0) | PATHS[path] | (MAC_COM if com else 0)
         nc, nl = C.c_int64(), C.c_int64()
         _check(lib().octgrav_lists_ex(self._h, float(theta), fl, None, None, None, None,
                                       C.byref(nc), C.byref(nl)))

@@ -1,0 +1,81 @@
+"""The centre-of-mass offset opening test on the GPU (OCTGRAV_MAC_COM, fused
+wave path) against the oracle's walk with the same FP32 inputs (the library's
+exported centres of mass): lists bit-exact, forces within the gates of the
+oracle's FP64 evaluation of those lists, argument rules."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1005_5384_amd import octgrav as og
+from paper_1005_5384_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _check(T, O, theta, eps):
+    torch = _torch()
+    com = T.export()["mp"][:, :3]
+    ref = O.lists_com(theta, com)
+    got = T.lists(theta, com=True)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    acc, pot = T.forces(theta, eps, com=True)
+    torch.cuda.synchronize()
+    ar, pr = O.forces_lists(ref, eps)
+    ea = oracle.rel_err(acc.double().cpu().numpy(), ar)
+    ep = oracle.rel_err(pot.double().cpu().numpy(), pr)
+    assert np.median(ea) <= 1e-5 and ea.max() <= 1e-4, (theta, np.median(ea), ea.max())
+    assert np.median(ep) <= 1e-5 and ep.max() <= 1e-4, (theta, np.median(ep), ep.max())
+    return ref
+
+
+@pytest.mark.parametrize("gen,n,n_leaf,n_group", [("plummer", 16384, 16, 64),
+                                                  ("clumps", 20000, 8, 32),
+                                                  ("milky_way", 12000, 1, 1)])
+def test_offset_lists_and_forces(gen, n, n_leaf, n_group):
+    pos, m = {"plummer": lambda: W.plummer(n, 31), "clumps": lambda: W.plummer_clumps(n, 32),
+              "milky_way": lambda: W.milky_way(n, 33)}[gen]()
+    T = og.Tree(pos, m, n_leaf, n_group)
+    O = oracle.Tree(pos, m, n_leaf, n_group)
+    for theta in (0.0, 0.3, 0.5, 0.57):
+        ref = _check(T, O, theta, 1e-3)
+        if theta == 0.0:  # no offset matters when every sized cell opens
+            for a, b in zip(ref, O.lists(0.0)):
+                assert np.array_equal(a, b)
+
+
+def test_offset_on_device_built_tree_and_theta_changes():
+    pos, m = W.plummer(30000, 34)
+    T = og.Tree(pos, m, 16, 64, device_build=True)
+    O = oracle.Tree(pos, m, 16, 64)
+    _check(T, O, 0.4, 1e-3)
+    _check(T, O, 0.55, 1e-3)   # records remade for the new angle
+    _check(T, O, 0.4, 1e-3)
+    # the default test is untouched by the offset calls
+    for a, b in zip(T.lists(0.5), O.lists(0.5)):
+        assert np.array_equal(a, b)
+
+
+def test_offset_argument_rules():
+    pos, m = W.plummer(2000, 35)
+    T = og.Tree(pos, m)
+    with pytest.raises(og.OctgravError):
+        T.forces(0.6, 1e-3, com=True)
+    with pytest.raises(og.OctgravError):
+        T.forces(0.5, 1e-3, com=True, path="two_pass")
+    with pytest.raises(og.OctgravError):
+        T.forces(0.5, 1e-3, com=True, path="fused_block")
+    with pytest.raises(og.OctgravError):
+        T.lists(0.6, com=True)
+    from paper_1005_5384_amd import learned as L
+    T.set_mac(og.Mlp(L.load_params()), 0.4, 0.8, 4e-4, 1e-2)
+    with pytest.raises(og.OctgravError):
+        T.forces(0.5, 1e-3, com=True)
+    T.set_mac(None)
+    T.forces(0.5, 1e-3, com=True, path="fused_wave")
