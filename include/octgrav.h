@@ -133,7 +133,7 @@ octgrav_tree* octgrav_build_tree_ex(const float* pos, const float* mass, int64_t
  *   pot    device, n FP32, caller's order (written), or NULL
  * Runs on the handle's stream and returns once the results are complete on it.
  * All paths evaluate the same lists; the default picks the fastest measured
- * one for theta (the fused block walk below 0.43, the fused wave walks above).
+ * one for theta (the fused block walk below 0.40, the fused wave walks above).
  */
 int octgrav_forces(octgrav_tree* t, float theta, float eps, float* acc, float* pot);
 

@@ -549,17 +549,16 @@ enum class Path { TwoPass, FusedBlock, FusedWave };
 
 // Path of a call: an explicit flag, else the fastest measured for theta
 // (2^20 Plummer, 4M clumps and 2^20 Milky-Way-like sets; ms at theta 0.38 /
-// 0.42 / 0.44 / 0.46, fused block: Plummer 6.3 / 5.1 / 4.7 / 3.8, clumps
-// 24.7 / 19.9 / 18.0 / 15.0, Milky Way 8.8 / 7.0 / 6.3 / 5.0; fused wave:
-// 7.8 / 6.3 / 4.1 / 3.2, 32.2 / 16.9 / 14.7 / 12.7, 9.6 / 6.3 / 5.1 / 3.9;
-// the two-pass path trails both).  Below 0.4 the wave variant needs its
-// 4096-entry LDS queues, which allow only a few walks per CU, where the block
-// variant shares one queue among four waves.
+// 0.40 / 0.42, fused block: Plummer 6.3 / 5.5 / 5.1, clumps 24.7 / 21.7 /
+// 19.9, Milky Way 8.8 / 7.4 / 7.0; fused wave: 8.2 / 5.4 / 4.6, 25.0 / 17.4 /
+// 15.7, 9.5 / 6.1 / 5.4; the two-pass path trails both).  At small angles the
+// wave variant's 4096-entry LDS queues allow only a few walks per CU, where
+// the block variant shares one queue among four waves.
 static Path choose_path(uint32_t flags, float theta) {
   if (flags & OCTGRAV_TWO_PASS) return Path::TwoPass;
   if (flags & OCTGRAV_FUSED_BLOCK) return Path::FusedBlock;
   if (flags & OCTGRAV_FUSED_WAVE) return Path::FusedWave;
-  return theta < 0.43f ? Path::FusedBlock : Path::FusedWave;  // measured crossover
+  return theta < 0.40f ? Path::FusedBlock : Path::FusedWave;  // measured crossover
 }
 
 static int launch_fused(const octgrav_tree* t, Path p, float theta, float eps, bool plain,

@@ -485,14 +485,14 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
   // The breadth-first FIFO holds about two tree levels of the group's walk,
   // which grows like theta^-3: 1024 entries hold most walks at theta >= 0.4 on
   // 2^20-particle sets (peak ~740 at 0.5 on a Plummer sphere), 4096 the
-  // smaller angles.  Tiers: 1024-entry LDS queues (theta >= 0.4 and the
+  // smaller angles.  Tiers: 1024-entry LDS queues (theta >= 0.37 and the
   // learned criterion; 16, or 12 with the network, waves per CU), then the
-  // overflows with 4096-entry LDS queues (one wave per block), then
-  // global-memory queues.  Below 0.4 so many walks overflow the first tier
+  // overflows with 4096-entry LDS queues (one wave per block, 7 per CU), then
+  // global-memory queues.  Below 0.37 so many walks overflow the first tier
   // that starting with the 4096-entry queues is faster (2^20 Plummer at
-  // 0.35: 9.6 instead of 35 ms).
+  // 0.35: 9.6 instead of 12.8 ms; 4M clumps at 0.38: 25.0 instead of 32.1).
   const bool learned = B.mlp != nullptr;
-  const bool wide = theta < 0.40f && !learned;
+  const bool wide = theta < 0.37f && !learned;
   auto go = [&](auto plain_tag, auto learned_tag) {
     constexpr bool P = decltype(plain_tag)::value, L = decltype(learned_tag)::value;
     if (wide) {
@@ -505,7 +505,7 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
       else  // 4 blocks of 4 waves per CU
         walk_eval_persistent_kernel<P, 1024, L, 4, false><<<8 * 128, 4 * kLanes, 0, s>>>(
             T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list, B.ovf_count);
-      walk_eval_persistent_kernel<P, 4096, L, 1, true><<<8 * 64, kLanes, 0, s>>>(
+      walk_eval_persistent_kernel<P, 4096, L, 1, true><<<8 * 224, kLanes, 0, s>>>(
           T, B, th2, eps2, acc, pot, do_eval, B.ovf_list, B.ovf_count, B.ovf_list2, B.ovf_count2);
     }
     walk_eval_fallback_kernel<P, L><<<B.gq_waves, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval,
