@@ -156,11 +156,17 @@ def W_sample(n, w):
     return W.sample_indices(n, w.get("sample", 4096), w.get("sample_seed", 4096))
 
 
-def learned_vs_theta(T, w, steps, band=(0.4, 0.8), beta=30.0, target=1e-3, params=None):
+def learned_vs_theta(T, w, steps, band=None, beta=30.0, target=1e-3, params=None,
+                     band_rel=(-0.03, 0.25)):
     """The learned acceptance criterion against the opening angle at equal
     p99 relative force error (against the GPU direct sum on the 4096-particle
     sample): theta* by bisection, then tau_pair (budget = beta * tau_pair) by
-    bisection in log tau, then both timed over `steps` force calls."""
+    bisection in log tau, then both timed over `steps` force calls.  The
+    network decides in the band (theta* + a, theta* + b), band_rel = (a, b),
+    or in the fixed `band` when one is given.
+    The target is unreachable when the band's lower edge exceeds theta*
+    (everything that edge accepts is accepted): `target_met` says whether the
+    learned operating point met it."""
     import torch
     from paper_1005_5384_amd import learned as L
     from paper_1005_5384_amd import octgrav as og
@@ -188,6 +194,8 @@ def learned_vs_theta(T, w, steps, band=(0.4, 0.8), beta=30.0, target=1e-3, param
     t_th = timed(th)
     c_th = T.last_counts()
     log(f"bench: theta* {th:.4f} p99 {e_th:.3e} {t_th * 1e3:.3f} ms")
+    if band is None:
+        band = (min(1.0, max(0.0, th + band_rel[0])), min(1.0, th + band_rel[1]))
     net = og.Mlp(L.load_params() if params is None else L.load_params(params))
 
     def p99_tau(lt):
@@ -213,6 +221,7 @@ def learned_vs_theta(T, w, steps, band=(0.4, 0.8), beta=30.0, target=1e-3, param
                     "band_scored": st["band"], "groups_fell_back": st["fell_back"],
                     "groups": T.stats["n_groups"]},
         "speedup": t_th / t_l,
+        "target_met": bool(e_l <= target),
     }
 
 
@@ -231,7 +240,15 @@ def main():
     ap.add_argument("--mac", default="theta", choices=["theta", "learned"],
                     help="acceptance criterion of the timed steps")
     ap.add_argument("--tau", type=float, default=4.21e-4,
-                    help="tau_pair of --mac learned (band 0.4-0.8, budget 30 tau)")
+                    help="tau_pair of --mac learned (budget --beta x tau)")
+    ap.add_argument("--band", type=float, nargs=2, default=None, metavar=("LO", "HI"),
+                    help="opening angles bounding the learned criterion's band (--mac learned: "
+                         "default 0.4 0.8; learned-vs-theta: default theta*-0.03, theta*+0.25)")
+    ap.add_argument("--band-rel", type=float, nargs=2, default=(-0.03, 0.25), metavar=("A", "B"),
+                    help="learned-vs-theta comparison: band (theta* + A, theta* + B) unless "
+                         "--band is given")
+    ap.add_argument("--beta", type=float, default=30.0,
+                    help="group budget of the learned criterion in units of tau_pair")
     ap.add_argument("--params", default=None,
                     help="network parameters of the learned criterion (.npy, 5057 float32; "
                          "default: the shipped network)")
@@ -291,7 +308,8 @@ def main():
     if args.mac == "learned":
         from paper_1005_5384_amd import learned as L
         net = og.Mlp(L.load_params() if args.params is None else L.load_params(args.params))
-        T.set_mac(net, 0.4, 0.8, args.tau, 30.0 * args.tau)
+        band = tuple(args.band) if args.band else (0.4, 0.8)
+        T.set_mac(net, band[0], band[1], args.tau, args.beta * args.tau)
 
     for _ in range(args.warmup):
         T.forces(theta, eps, acc=acc, pot=pot, timed=True, path=args.path)
@@ -363,8 +381,8 @@ def main():
                           "frac": hw / eval_s / 1e12 / PEAK_FP32_TFLOPS,
                           "counters": "SQ_INSTS_VALU_FLOPS_FP32 + SQ_INSTS_VALU_FLOPS_FP32_TRANS"}
     if args.mac == "learned":
-        out["config"].update({"tau_pair": args.tau, "theta_lo": 0.4, "theta_hi": 0.8,
-                              "budget": 30.0 * args.tau})
+        out["config"].update({"tau_pair": args.tau, "theta_lo": band[0],
+                              "theta_hi": band[1], "budget": args.beta * args.tau})
         out["mac_stats"] = T.mac_stats()
         T.set_mac(None)
     if args.list_spread or (args.workload == "clumps4m" and args.mac == "theta"):
@@ -375,7 +393,9 @@ def main():
         out["integration"] = integration_rate(n, theta, eps, args.steps)
     if not args.no_learned:
         log("bench: learned criterion vs theta at p99 1e-3 ...")
-        out["learned_vs_theta"] = learned_vs_theta(T, w, args.steps, params=args.params)
+        out["learned_vs_theta"] = learned_vs_theta(
+            T, w, args.steps, band=tuple(args.band) if args.band else None, beta=args.beta,
+            params=args.params, band_rel=tuple(args.band_rel))
     # FP32 plain accumulation (no compensation) on the same call, for comparison
     plain = None
     if args.mac == "theta":
