@@ -171,6 +171,196 @@ __global__ void emit_kernel(Cells C, int64_t lbeg, int64_t lend, int64_t m, int 
     }
 }
 
+// ---- subdivision without host round trips: every level's range lives on
+// the device, so all levels are launched back to back.
+struct Level {
+  int64_t beg, end;   // the level's cells [beg, end)
+  int64_t total;      // children it emitted
+  int32_t overflow;   // the cell arrays could not hold them
+  int32_t pad;
+};
+constexpr int kLB = 512;  // blocks of the level kernels; block b owns a contiguous chunk
+
+// Eight lanes per cell: lane d of the group finds the first particle of the
+// cell whose octant digit at level L is >= d (d = 0: the cell's first), all
+// eight searches at once; the next lane's boundary closes the octant.
+// Returns whether octant d is a non-empty child (false for leaves).
+struct OctantLane {
+  int64_t c;
+  int32_t lo, hi;  // the octant's particles [lo, hi)
+  bool child;
+};
+__device__ OctantLane octant_lane(const Cells& C, const uint64_t* __restrict__ key, int64_t beg,
+                                  int64_t j, bool valid, int L, int n_leaf) {
+  const int d = threadIdx.x & 7;
+  OctantLane o{beg + j, 0, 0, false};
+  int32_t a = 0, b = 0;
+  bool split = false;
+  if (valid) {
+    a = C.first[o.c];
+    b = a + C.n[o.c];
+    split = !(C.n[o.c] <= n_leaf || L == kMaxDepth);
+  }
+  int32_t l = a;
+  if (split && d > 0) {
+    const int sh = 3 * (kMaxDepth - 1 - L);
+    int32_t h = b;
+    while (l < h) {
+      const int32_t mid = l + ((h - l) >> 1);
+      if ((int)((key[mid] >> sh) & 7) < d) l = mid + 1;
+      else h = mid;
+    }
+  }
+  const int32_t nx = __shfl_down(l, 1, 8);
+  o.lo = l;
+  o.hi = d == 7 ? b : nx;
+  o.child = split && o.hi > o.lo;
+  return o;
+}
+
+// Non-empty children among the eight lanes of this lane's group, and how many
+// of them come before this lane.
+__device__ void octant_counts(bool child, int* n, int* before) {
+  const uint64_t m = __ballot(child);
+  const int lane = threadIdx.x & 63, g = lane & ~7;
+  const uint32_t grp = (uint32_t)(m >> g) & 0xffu;
+  *n = __popc(grp);
+  *before = __popc(grp & ((1u << (lane - g)) - 1u));
+}
+
+// Sum of v over the block (kT threads); every thread gets it.
+__device__ int block_sum(int v, int* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+  for (int k = 0; k < kT / 64; ++k) t += sh[k];
+  __syncthreads();
+  return t;
+}
+
+// Exclusive prefix of v over the block in thread order, and the block total.
+__device__ int block_exclusive(int v, int* total, int* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) sh[w] = incl;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int k = 0; k < kT / 64; ++k) {
+    base += k < w ? sh[k] : 0;
+    tot += sh[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + incl - v;
+}
+
+__global__ void level_init_kernel(Cells C, Level* lv, int32_t n) {
+  if (threadIdx.x == 0) {
+    C.first[0] = 0;
+    C.n[0] = n;
+    C.depth[0] = 0;
+    C.parent[0] = -1;
+    C.fc[0] = -1;
+    C.nc[0] = 0;
+  }
+  if (threadIdx.x < kMaxDepth + 2) {
+    const int64_t e = threadIdx.x == 0 ? 1 : 0;
+    lv[threadIdx.x] = Level{0, e, 0, 0, 0};
+  }
+}
+
+// Children counts of level L's cells (nkid[j] for cell beg + j) and per-block
+// sums; eight lanes per cell.
+__global__ __launch_bounds__(kT) void split_level_kernel(Cells C, const uint64_t* __restrict__ key,
+                                                         const Level* __restrict__ lv, int L,
+                                                         int n_leaf, int32_t* __restrict__ nkid,
+                                                         int32_t* __restrict__ bsum) {
+  __shared__ int sh[kT / 64];
+  const int64_t beg = lv[L].beg, m = lv[L].end - beg;
+  const int64_t chunk = (m + kLB - 1) / kLB;
+  const int64_t j0 = blockIdx.x * chunk, j1 = j0 + chunk < m ? j0 + chunk : m;
+  int s = 0;
+  for (int64_t base = j0; base < j1; base += kT / 8) {
+    const int64_t j = base + threadIdx.x / 8;
+    const OctantLane o = octant_lane(C, key, beg, j, j < j1, L, n_leaf);
+    int k, before;
+    octant_counts(o.child, &k, &before);
+    if ((threadIdx.x & 7) == 0 && j < j1) {
+      nkid[j] = k;
+      s += k;
+    }
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+}
+
+// Exclusive scan of the block sums, the level's total, the capacity check,
+// and the next level's range (empty after an overflow).
+__global__ __launch_bounds__(kT) void level_scan_kernel(int32_t* __restrict__ bsum,
+                                                        Level* __restrict__ lv, int L,
+                                                        int64_t cap) {
+  __shared__ int sh[kT / 64];
+  static_assert(kLB == 2 * kT, "two block sums per thread");
+  const int a = bsum[2 * threadIdx.x], b = bsum[2 * threadIdx.x + 1];
+  int total = 0;
+  const int ex = block_exclusive(a + b, &total, sh);
+  bsum[2 * threadIdx.x] = ex;
+  bsum[2 * threadIdx.x + 1] = ex + a;
+  if (threadIdx.x == 0) {
+    const int64_t end = lv[L].end;
+    const int over = lv[L].overflow || end + total > cap;
+    lv[L].total = over ? 0 : total;
+    lv[L].overflow = over;
+    if (L + 1 < kMaxDepth + 2) lv[L + 1] = Level{end, over ? end : end + total, 0, over, 0};
+  }
+}
+
+// Writes level L's children in cell order (the scan's numbering); eight
+// lanes per cell, one per octant.
+__global__ __launch_bounds__(kT) void emit_level_kernel(Cells C, const uint64_t* __restrict__ key,
+                                                        const Level* __restrict__ lv, int L,
+                                                        int n_leaf,
+                                                        const int32_t* __restrict__ nkid,
+                                                        const int32_t* __restrict__ bsum) {
+  __shared__ int sh[kT / 64];
+  if (lv[L].overflow) return;
+  const int64_t beg = lv[L].beg, end = lv[L].end, m = end - beg;
+  const int64_t chunk = (m + kLB - 1) / kLB;
+  const int64_t j0 = blockIdx.x * chunk, j1 = j0 + chunk < m ? j0 + chunk : m;
+  int64_t carry = bsum[blockIdx.x];
+  for (int64_t base = j0; base < j1; base += kT / 8) {
+    const int64_t j = base + threadIdx.x / 8;
+    const bool valid = j < j1;
+    const OctantLane o = octant_lane(C, key, beg, j, valid, L, n_leaf);
+    int k, before;
+    octant_counts(o.child, &k, &before);
+    const bool lead = (threadIdx.x & 7) == 0;
+    int step = 0;
+    const int ex = __shfl(block_exclusive(lead && valid ? k : 0, &step, sh),
+                          (int)(threadIdx.x & 63) & ~7);
+    const int64_t first = end + carry + ex;
+    if (lead && valid && k > 0) {
+      C.fc[o.c] = (int32_t)first;
+      C.nc[o.c] = k;
+    }
+    if (o.child) {
+      const int64_t ch = first + before;
+      C.first[ch] = o.lo;
+      C.n[ch] = o.hi - o.lo;
+      C.depth[ch] = L + 1;
+      C.parent[ch] = (int32_t)o.c;
+      C.fc[ch] = -1;
+      C.nc[ch] = 0;
+    }
+    carry += step;
+  }
+}
+
 __global__ void gather_kernel(const float* __restrict__ pos, const float* __restrict__ mass,
                               const int32_t* __restrict__ perm, int64_t n,
                               float4* __restrict__ part, int32_t* __restrict__ iperm) {
@@ -525,13 +715,45 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
     return true;
   };
   if (!grow(cap)) return fail("device allocation failed");
-  const int32_t root[6] = {0, (int32_t)n, 0, -1, -1, 0};
-  int32_t* rdst[6] = {C.first, C.n, C.depth, C.parent, C.fc, C.nc};
-  for (int k = 0; k < 6; ++k)
-    if (hipMemcpyAsync(rdst[k], &root[k], 4, hipMemcpyHostToDevice, s) != hipSuccess)
-      return fail("root upload failed");
   std::vector<int64_t> level_beg{0};
   int64_t lbeg = 0, lend = 1;
+  // All levels back to back with their ranges on the device (no host round
+  // trip per level); a tree that outgrows the cell arrays is redone below
+  // level by level, growing them.
+  {
+    Level* lv = S.get<Level>(kMaxDepth + 2);
+    int32_t* nkid = S.get<int32_t>(cap);
+    int32_t* bsum = S.get<int32_t>(kLB);
+    if (!lv || !nkid || !bsum) return fail("device allocation failed");
+    level_init_kernel<<<1, 64, 0, s>>>(C, lv, (int32_t)n);
+    for (int L = 0; L <= kMaxDepth; ++L) {
+      split_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum);
+      level_scan_kernel<<<1, kT, 0, s>>>(bsum, lv, L, cap);
+      emit_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum);
+    }
+    std::vector<Level> hl(kMaxDepth + 2);
+    if (hipMemcpyAsync(hl.data(), lv, hl.size() * sizeof(Level), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail("subdivision failed");
+    bool over = false;
+    for (const Level& v : hl) over = over || v.overflow;
+    if (!over) {
+      for (int L = 0; L <= kMaxDepth && hl[L].end > hl[L].beg; ++L) {
+        h.max_level_cells = std::max(h.max_level_cells, hl[L].end - hl[L].beg);
+        if (hl[L].total > 0) h.max_depth = L + 1;
+        level_beg.push_back(hl[L].end);
+        lbeg = lend = hl[L].end;
+      }
+    }
+  }
+  if (lbeg < lend) {  // the arrays overflowed: level by level with growth
+    const int32_t root[6] = {0, (int32_t)n, 0, -1, -1, 0};
+    int32_t* rdst[6] = {C.first, C.n, C.depth, C.parent, C.fc, C.nc};
+    for (int k = 0; k < 6; ++k)
+      if (hipMemcpyAsync(rdst[k], &root[k], 4, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail("root upload failed");
+  }
   for (int L = 0; lbeg < lend; ++L) {
     const int64_t m = lend - lbeg;
     if (pools) pools->level.rewind();  // the previous level's scratch is dead

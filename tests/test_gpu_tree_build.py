@@ -72,3 +72,17 @@ def test_device_build_rejects_bad_input():
         og.Tree(pos, m, device_build=True)
     with pytest.raises(og.OctgravError):
         og.Tree(W.plummer(100, 1)[0], m, host_only=True, device_build=True)
+
+
+def test_device_build_deep_chains_outgrow_the_cell_arrays():
+    # pairs of coincident particles with one particle per leaf: each pair is a
+    # chain of single-child cells down to depth 21, far more cells than 2n + 64,
+    # so the subdivision that keeps its level ranges on the device overflows and
+    # the build redoes it level by level; the tree must still be the host's
+    _torch()
+    rng = np.random.default_rng(17)
+    base = rng.uniform(-1, 1, (96, 3)).astype(np.float32)
+    pos = np.concatenate([base, base, rng.uniform(-1, 1, (40, 3)).astype(np.float32)])
+    m = rng.uniform(0.5, 1.5, pos.shape[0]).astype(np.float32)
+    H, D = _same_tree(pos, m, 1, 1)
+    assert H.stats["n_cells"] > 2 * pos.shape[0] + 64
