@@ -82,8 +82,25 @@ def cpu_baseline(pos, m, w, gpu_acc, gpu_pot, plain=None):
     t0 = time.perf_counter()
     ad, _ = oracle.direct(pos, m, w["eps"], targets=tg)
     t_direct = time.perf_counter() - t0
+    # One core: the same-tree walk and evaluation of the groups that hold the
+    # sampled particles only (a bounded sample of the same call).
+    ex = O.export()
+    first = ex["topo"][ex["groups"], 2].astype(np.int64)
+    rank = np.empty(n, np.int64)
+    rank[ex["order"]] = np.arange(n)
+    sel = np.unique(np.searchsorted(first, rank[tg], side="right") - 1).astype(np.int32)
+    n_sel = int(ex["topo"][ex["groups"][sel], 3].sum())
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    O.forces(0.5, w["eps"], groups=sel)
+    t_one = time.perf_counter() - t0
+    oracle.set_threads(cores)
     return {
         "value": n / t_eval, "unit": "particles/s", "cores": cores, "kind": "oracle",
+        "one_core": {"value": n_sel / t_one, "unit": "particles/s", "cores": 1,
+                     "sample": f"the {len(sel)} groups ({n_sel} particles) holding the "
+                               f"{len(tg)} sampled particles, same-tree walk + FP64 evaluation, "
+                               f"{t_one:.2f} s"},
         "sample": (f"the whole 2^20 Plummer force call at theta=0.5 (same-tree FP64 walk + "
                    f"evaluation of all {O.n_groups} groups, {t_eval:.2f} s); oracle tree build "
                    f"{t_build:.2f} s; FP64 direct sum of the {len(tg)} sampled particles "

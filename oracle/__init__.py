@@ -52,6 +52,7 @@ def lib():
                                        _f64p, vp]
         L.orc_diagnostics.argtypes = [_f32p, _f64p, vp, C.c_int64, _f64p]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_mlp_params.restype = C.c_int
         L.orc_mac_features.argtypes = [vp, _i32p, _i32p, C.c_int64, _f32p]
         L.orc_mac_band.argtypes = [vp, C.c_float, C.c_float, vp, C.c_int64, vp, vp, C.c_int64,
@@ -79,6 +80,11 @@ def _pos(pos):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().orc_set_threads(int(k))
 
 
 def direct(pos, mass, eps, targets=None):

@@ -796,4 +796,7 @@ int orc_diagnostics(const float* mass, const double* acc, const double* pot, int
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
 
+// Threads of the oracle's parallel loops from now on (k >= 1).
+void orc_set_threads(int k) { omp_set_num_threads(k < 1 ? 1 : k); }
+
 }  // extern "C"
