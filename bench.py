@@ -278,8 +278,9 @@ def main():
                          "(the reference for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(one process drives one GPU; the path shards by groups over a replicated tree)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library "
+              "drives one GPU per process; a multi-GPU run would shard the groups over a "
+              "replicated tree)", file=sys.stderr)
         sys.exit(2)
 
     import torch
