@@ -44,6 +44,9 @@ __device__ __forceinline__ bool open_cell(float4 gmin, float4 gmax, float4 c, fl
 // and potential -m_j / r~, r~^2 = |x_j - x_i|^2 + eps^2.
 __device__ __forceinline__ void pp_term(const float4 xi, const float4 sj, float eps2, float& ax,
                                         float& ay, float& az, float& ph) {
+  // No contraction: the potential term m_j / r~ is rounded once before it is
+  // subtracted, so the self pair's contribution equals self_term() exactly.
+#pragma clang fp contract(off)
   const float dx = sj.x - xi.x, dy = sj.y - xi.y, dz = sj.z - xi.z;
   const float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
   const float ri = __builtin_amdgcn_rsqf(r2);
@@ -53,6 +56,13 @@ __device__ __forceinline__ void pp_term(const float4 xi, const float4 sj, float 
   ay = fmaf(mri3, dy, ay);
   az = fmaf(mri3, dz, az);
   ph -= mri;
+}
+
+// The self pair's potential term m_i / eps, rounded exactly as pp_term rounds
+// it (the walks evaluate the pair j = i and take this value back out).
+__device__ __forceinline__ float self_term(float m, float eps2) {
+#pragma clang fp contract(off)
+  return m * __builtin_amdgcn_rsqf(eps2);
 }
 
 // Particle-cell (body-node) term: softened monopole + traceless quadrupole

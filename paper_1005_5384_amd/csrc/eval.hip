@@ -175,7 +175,7 @@ __device__ void eval_item(const DevTree& T, const WalkBufs& B, EvalShared& es, f
     // The leaf list holds the target itself; its self term contributed
     // -m_i/eps to the potential and nothing to the acceleration.  Remove it
     // with the identical FP32 value.
-    const float self = xi.w * __builtin_amdgcn_rsqf(eps2);
+    const float self = self_term(xi.w, eps2);
     if (PLAIN) s[3] += self;
     else neu_add(s[3], c[3], self);
     const int o = T.perm[first + tid];

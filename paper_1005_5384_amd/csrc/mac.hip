@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kThreads) void direct_kernel(DevTree T, const int32
     __syncthreads();
   }
   if (act) {
-    neu_add(s.s[3], s.c[3], xi.w * __builtin_amdgcn_rsqf(eps2));
+    neu_add(s.s[3], s.c[3], self_term(xi.w, eps2));
     acc[3 * u + 0] = s.s[0] + s.c[0];
     acc[3 * u + 1] = s.s[1] + s.c[1];
     acc[3 * u + 2] = s.s[2] + s.c[2];

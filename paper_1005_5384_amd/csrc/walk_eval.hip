@@ -345,7 +345,7 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
     }
     // The target itself is in its own leaf: its self term added -m_i/eps to
     // the potential and nothing to the acceleration; remove that same value.
-    const float self = it.xi.w * __builtin_amdgcn_rsqf(eps2);
+    const float self = self_term(it.xi.w, eps2);
     if (PLAIN) s[3] += self;
     else neu_add(s[3], cc[3], self);
     const int64_t o = T.perm[first + lane];

@@ -1,0 +1,65 @@
+"""Seeded random configurations through every walk: particle counts from 1
+to 6000 in Plummer, clumped, Milky-Way-like and lattice (plane ties,
+coincident points) layouts, random leaf and group capacities and opening
+angles.  Lists of the three paths, of the device-built tree and of the
+offset test must equal the oracle's bit for bit, and forces must meet the
+gates of the same-tree FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1005_5384_amd import octgrav as og
+from paper_1005_5384_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(k):
+    rng = np.random.default_rng(1000 + k)
+    n = int(rng.choice([1, 2, 3, 7, 64, 65, 500, 1999, 4096, 6000]))
+    kind = ["plummer", "clumps", "milky_way", "lattice"][k % 4]
+    if kind == "plummer":
+        pos, m = W.plummer(n, 2000 + k)
+    elif kind == "clumps":
+        pos, m = W.plummer_clumps(n, 2000 + k, n_clumps=5)
+    elif kind == "milky_way":
+        pos, m = W.milky_way(n, 2000 + k)
+    else:
+        pos = (rng.integers(-3, 4, (n, 3)) * 0.5).astype(np.float32)
+        m = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    n_leaf = int(rng.choice([1, 2, 8, 16, 33, 64]))
+    n_group = int(rng.choice([1, 5, 16, 64, 100, 1024]))
+    theta = float(rng.choice([0.0, 0.2, 0.35, 0.41, 0.5, 0.57, 0.8, 1.0]))
+    return pos, m, n_leaf, n_group, theta
+
+
+@pytest.mark.parametrize("k", range(32))
+def test_random_configuration(k):
+    import torch
+    assert torch.cuda.is_available()
+    pos, m, n_leaf, n_group, theta = _case(k)
+    O = oracle.Tree(pos, m, n_leaf, n_group)
+    ref = O.lists(theta)
+    for dev in (False, True):
+        T = og.Tree(pos, m, n_leaf, n_group, device_build=dev)
+        for path in (None, "two_pass", "fused_block", "fused_wave"):
+            for a, b in zip(T.lists(theta, path=path), ref):
+                assert np.array_equal(a, b), (k, dev, path)
+        if theta <= 0.57:
+            com = T.export()["mp"][:, :3]
+            for a, b in zip(T.lists(theta, com=True), O.lists_com(theta, com)):
+                assert np.array_equal(a, b), (k, dev, "com")
+        acc, pot = T.forces(theta, 0.01)
+        torch.cuda.synchronize()
+        ar, pr = O.forces(theta, 0.01)
+        a, p = acc.double().cpu().numpy(), pot.double().cpu().numpy()
+        if pos.shape[0] > 1:
+            na = np.linalg.norm(ar, axis=1)
+            keep = na >= 1e-6 * np.median(na)
+            ea = oracle.rel_err(a[keep], ar[keep])
+            ep = oracle.rel_err(p, pr)
+            assert np.median(ea) <= 1e-5 and ea.max() <= 1e-4, (k, dev, ea.max())
+            assert np.median(ep) <= 1e-5 and ep.max() <= 1e-4, (k, dev, ep.max())
+        else:
+            assert np.all(a == 0) and np.all(p == 0)
+        T.close()
