@@ -63,3 +63,46 @@ def test_random_configuration(k):
         else:
             assert np.all(a == 0) and np.all(p == 0)
         T.close()
+
+
+@pytest.mark.parametrize("k", range(10))
+def test_random_learned_configuration(k):
+    """The learned criterion on seeded random trees, bands, tau_pair and
+    budgets: the walk's exported decisions replayed by the oracle give the
+    same lists and the same fall-backs, and the forces of those lists meet
+    the gates of the oracle's FP64 evaluation."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1005_5384_amd import learned as L
+    rng = np.random.default_rng(3000 + k)
+    pos, m, n_leaf, n_group, _ = _case(k)
+    lo = float(rng.choice([0.3, 0.4, 0.5]))
+    hi = lo + float(rng.choice([0.2, 0.3, 0.45]))
+    theta = float(rng.choice([0.4, 0.55, 0.7]))
+    tau = float(10.0 ** rng.uniform(-5, -2))
+    budget = float(rng.choice([-1.0, 3 * tau, 30 * tau, 1e9]))
+    T = og.Tree(pos, m, n_leaf, n_group, device_build=bool(k % 2))
+    O = oracle.Tree(pos, m, n_leaf, n_group)
+    T.set_mac(og.Mlp(L.load_params()), lo, hi, tau, budget)
+    off, cells, scores, fb = T.mac_trace(theta)
+    g = np.repeat(np.arange(off.size - 1, dtype=np.int32), np.diff(off))
+    ref, rfb = O.lists_learned(theta, lo, hi, float(np.float32(np.log10(np.float32(tau)))), budget,
+                               replay=(g, cells, scores))
+    got = T.lists(theta)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b), k
+    assert np.array_equal(fb, rfb), k
+    if budget < 0:
+        assert np.all(fb == 1) or fb.size == 0
+    acc, pot = T.forces(theta, 0.01)
+    torch.cuda.synchronize()
+    ar, pr = O.forces_lists(ref, 0.01)
+    if pos.shape[0] > 1:
+        na = np.linalg.norm(ar, axis=1)
+        keep = na >= 1e-6 * np.median(na)
+        ea = oracle.rel_err(acc.double().cpu().numpy()[keep], ar[keep])
+        ep = oracle.rel_err(pot.double().cpu().numpy(), pr)
+        assert np.median(ea) <= 1e-5 and ea.max() <= 1e-4, (k, ea.max())
+        assert np.median(ep) <= 1e-5 and ep.max() <= 1e-4, (k, ep.max())
+    T.set_mac(None)
+    T.close()
