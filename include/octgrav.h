@@ -291,7 +291,13 @@ int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells
  * A particle system on the device, advanced with kick-drift-kick leapfrog
  * (v += a dt/2, x += v dt, new tree and forces, v += a dt/2) in FP32; the
  * tree is rebuilt on the GPU from the drifted positions every step (as
- * OCTGRAV_BUILD_DEVICE, inputs never leave the device).
+ * OCTGRAV_BUILD_DEVICE, inputs never leave the device).  The handle owns the
+ * state and one tree that is rebuilt in place: its device buffers are kept
+ * and reused from step to step (a buffer is reallocated only when a tree
+ * outgrows it) until octgrav_sim_free.  Calls return OCTGRAV_OK or the codes
+ * above (OCTGRAV_EINVAL for bad arguments or positions that became
+ * non-finite, OCTGRAV_ENOMEM, OCTGRAV_EHIP), with octgrav_last_error()
+ * holding the message.  One handle must not be used by two threads at once.
  */
 typedef struct octgrav_sim octgrav_sim;
 
