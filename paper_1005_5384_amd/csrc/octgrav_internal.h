@@ -185,6 +185,7 @@ struct SeqPool {
 // per-level arrays (the same slots every level) and the cell arrays.
 struct BuildPools {
   SeqPool outer, level, cells;
+  int last_levels = 0;  // non-empty levels of the previous build (0: unknown)
 };
 struct DeviceArrays {
   const double* box = nullptr;     // [nc * 6]

@@ -726,25 +726,38 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
     int32_t* bsum = S.get<int32_t>(kLB);
     if (!lv || !nkid || !bsum) return fail("device allocation failed");
     level_init_kernel<<<1, 64, 0, s>>>(C, lv, (int32_t)n);
-    for (int L = 0; L <= kMaxDepth; ++L) {
-      split_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum);
-      level_scan_kernel<<<1, kT, 0, s>>>(bsum, lv, L, cap);
-      emit_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum);
-    }
+    // A rebuild launches the levels its previous tree had plus two, then
+    // looks whether the next one is empty (an empty level still costs three
+    // launches); the rest follow only if the tree turned out deeper.
     std::vector<Level> hl(kMaxDepth + 2);
-    if (hipMemcpyAsync(hl.data(), lv, hl.size() * sizeof(Level), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return fail("subdivision failed");
+    int L0 = 0, L1 = kMaxDepth;
+    if (pools && pools->last_levels > 0) L1 = std::min(kMaxDepth, pools->last_levels + 1);
+    for (;;) {
+      for (int L = L0; L <= L1; ++L) {
+        split_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum);
+        level_scan_kernel<<<1, kT, 0, s>>>(bsum, lv, L, cap);
+        emit_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum);
+      }
+      if (hipMemcpyAsync(hl.data(), lv, hl.size() * sizeof(Level), hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail("subdivision failed");
+      if (L1 == kMaxDepth || hl[L1 + 1].end == hl[L1 + 1].beg) break;
+      L0 = L1 + 1;
+      L1 = kMaxDepth;
+    }
     bool over = false;
     for (const Level& v : hl) over = over || v.overflow;
     if (!over) {
+      int levels = 0;
       for (int L = 0; L <= kMaxDepth && hl[L].end > hl[L].beg; ++L) {
         h.max_level_cells = std::max(h.max_level_cells, hl[L].end - hl[L].beg);
         if (hl[L].total > 0) h.max_depth = L + 1;
         level_beg.push_back(hl[L].end);
         lbeg = lend = hl[L].end;
+        levels = L + 1;
       }
+      if (pools) pools->last_levels = levels;
     }
   }
   if (lbeg < lend) {  // the arrays overflowed: level by level with growth
