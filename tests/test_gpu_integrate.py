@@ -95,3 +95,21 @@ def test_rebuilt_tree_matches_a_fresh_tree_after_collapse():
     r = np.linalg.norm(p, axis=1)
     assert np.median(r) < 0.6 * np.median(np.linalg.norm(pos, axis=1))
     assert st["n_cells"] != n_cells0
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 33, 300])
+def test_small_systems_match_oracle(n):
+    """Tiny systems (one particle drifting freely, a pair, a few bodies) at
+    theta = 0 against the FP64 direct-sum leapfrog."""
+    _torch()
+    rng = np.random.default_rng(40 + n)
+    pos = rng.normal(0, 1, (n, 3)).astype(np.float32)
+    vel = rng.normal(0, 0.3, (n, 3)).astype(np.float32)
+    m = rng.uniform(0.5, 1.5, n).astype(np.float32) / n
+    S = og.Sim(pos, vel, m, 4, 8)
+    S.run(0.0, 0.05, 1.0 / 128, 25)
+    p, v, _ = S.state()
+    rp, rv, _ = oracle.leapfrog(pos, vel, m, 0.05, 1.0 / 128, 25)
+    scale = max(1.0, float(np.abs(rp).max()))
+    assert np.abs(p - rp).max() < 2e-5 * scale, n
+    assert np.abs(v - rv).max() < 2e-5 * max(1.0, float(np.abs(rv).max())), n
