@@ -391,6 +391,9 @@ def main():
         "phases_ms": ph,
         "host_build_upload_s": t_build,
         "device_build_s": t_dev_build,
+        # one force call from host particles: tree build (+ upload) and the call
+        "end_to_end_ms": {"host_build": t_build * 1e3 + ms_step,
+                          "device_build": t_dev_build * 1e3 + ms_step},
         "tree": T.stats,
     }
     default_kernel = (args.workload == "plummer1m" and theta == 0.5 and args.path is None
