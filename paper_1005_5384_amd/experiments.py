@@ -9,6 +9,7 @@ configuration prints one JSON line.
     python -m paper_1005_5384_amd.experiments sweep [--workload plummer1m]
     python -m paper_1005_5384_amd.experiments errors
     python -m paper_1005_5384_amd.experiments mac [--workload plummer1m]
+    python -m paper_1005_5384_amd.experiments energy
 
 Errors are |a - a_ref| / |a_ref| (Sec. 3.1) on 4096 seeded sampled particles,
 a_ref from the library's compensated FP32 direct sum; percentiles are nearest
@@ -178,9 +179,34 @@ def _timed_mac(T, theta, eps, steps, com):
     return float(np.median(ms)), T.last_counts(), acc
 
 
+def energy_runs(n=1 << 20, thetas=(0.3, 0.5, 0.75), eps=1e-3, dt=1.0 / 256, steps=2048,
+                every=256, seed=102, out=sys.stdout):
+    """Energy conservation of the leapfrog with the tree rebuilt on the GPU
+    every step (an equilibrium Plummer sphere): relative energy change and
+    momentum drift every `every` steps, per opening angle."""
+    pos, vel, m = W.plummer_with_velocities(n, seed)
+    rows = []
+    for th in thetas:
+        S = og.Sim(pos, vel, m, 16, 64)
+        S.run(th, eps, dt, 0)
+        e0 = S.energy()
+        for k in range(every, steps + 1, every):
+            S.run(th, eps, dt, every)
+            e = S.energy()
+            r = {"experiment": "energy_runs", "n": n, "theta": th, "eps": eps, "dt": dt,
+                 "step": k, "t": k * dt, "dE_over_E": (e["E"] - e0["E"]) / abs(e0["E"]),
+                 "dP": float(np.linalg.norm(e["P"] - e0["P"])),
+                 "virial_2K_over_W": 2 * e["K"] / abs(e["W"]),
+                 "ms_per_step": S.timings()["step_ms"]}
+            print(json.dumps(r), file=out, flush=True)
+            rows.append(r)
+        S.close()
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("what", choices=["sweep", "errors", "mac"])
+    ap.add_argument("what", choices=["sweep", "errors", "mac", "energy"])
     ap.add_argument("--workload", default="plummer1m")
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--steps", type=int, default=5)
@@ -189,6 +215,8 @@ def main(argv=None):
         leaf_group_sweep(a.workload, a.theta, steps=a.steps)
     elif a.what == "mac":
         mac_variants(a.workload, steps=a.steps)
+    elif a.what == "energy":
+        energy_runs()
     else:
         error_curves(steps=a.steps)
 
