@@ -262,7 +262,8 @@ int octgrav_mlp_adam(octgrav_mlp* m, float lr, float beta1, float beta2, float e
  * default).  Otherwise a copy of m's current network is taken and, in later
  * octgrav_forces / octgrav_lists calls, a candidate the theta_lo test accepts
  * is accepted, one the theta_hi test opens is opened, and in between it is
- * accepted iff the network's output <= log10(tau_pair) (tau_pair = 0: never).
+ * accepted iff the network's output <= log10(tau_pair) (tau_pair = 0: never;
+ * the threshold is the FP64 log10 of the FP32 tau_pair rounded once to FP32).
  * A group whose network-accepted candidates have sqrt(sum 10^(2 y)) > budget
  * is walked with the call's theta instead (budget < 0: every group).
  * Needs 0 < theta_lo < theta_hi <= 1.  These calls then use the fused wave

@@ -110,6 +110,13 @@ def multipole_eval(pos, mass, target, eps, use_quad=True):
     return out[:3], out[3]
 
 
+def log10_threshold(tau) -> float:
+    """The FP32 threshold a network output is compared with under the learned
+    test (accept iff output <= it): the FP64 log10 of the FP32 tau_pair,
+    rounded once to FP32."""
+    return float(np.float32(np.log10(np.float64(np.float32(tau)))))
+
+
 def mac_open(gmin, gmax, geo, theta) -> bool:
     return bool(lib().orc_mac_open(np.asarray(gmin, np.float32), np.asarray(gmax, np.float32),
                                    np.asarray(geo, np.float32), float(theta)))

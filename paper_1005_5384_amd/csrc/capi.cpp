@@ -900,7 +900,9 @@ int octgrav_set_mac(octgrav_tree* t, const octgrav_mlp* m, float theta_lo, float
   t->wb.mlp = (const uint8_t*)t->d_mlp;
   t->wb.mac_lo2 = theta_lo * theta_lo;
   t->wb.mac_hi2 = theta_hi * theta_hi;
-  t->wb.mac_ltau = tau_pair > 0.0f ? std::log10(tau_pair) : -INFINITY;
+  // log10 tau_pair: the FP64 logarithm of the FP32 value, rounded once to FP32
+  // (reproducible anywhere; a float log10 may differ by an ulp between libraries)
+  t->wb.mac_ltau = tau_pair > 0.0f ? (float)std::log10((double)tau_pair) : -INFINITY;
   t->wb.mac_budget = (double)budget;
   return OCTGRAV_OK;
 }

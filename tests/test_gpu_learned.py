@@ -141,7 +141,7 @@ def setup():
 
 def _replay(R, theta, tau, budget, off, cells, scores):
     g = np.repeat(np.arange(off.size - 1, dtype=np.int32), np.diff(off))
-    return R.lists_learned(theta, 0.3, 1.0, float(np.float32(np.log10(np.float32(tau)))), budget,
+    return R.lists_learned(theta, 0.3, 1.0, oracle.log10_threshold(tau), budget,
                            replay=(g, cells, scores))
 
 
@@ -165,7 +165,7 @@ def test_learned_lists_replay_bit_exact(setup):
         gl = T.lists(0.6)
         _lists_equal(gl, ref)
         # the decisions are mixed: some band cells accepted, some opened
-        acc = scores <= np.log10(tau)
+        acc = scores <= np.float32(oracle.log10_threshold(tau))
         assert 0.2 < acc.mean() < 0.8
         st = T.mac_stats()
         assert st["band"] == cells.size and st["fell_back"] == 0
@@ -177,7 +177,7 @@ def test_learned_budget_fallback(setup):
     pos, m, T, R, P, net, tau = setup
     T.set_mac(net, 0.3, 1.0, tau, float("inf"))
     off, cells, scores, _ = T.mac_trace(0.6)
-    lt = np.float32(np.log10(np.float32(tau)))
+    lt = np.float32(oracle.log10_threshold(tau))
     # per-group budget sums of the accepted band candidates (FP64)
     term = np.where(scores <= lt, 10.0 ** (2.0 * scores.astype(np.float64)), 0.0)
     s2 = np.sqrt(np.add.reduceat(np.append(term, 0.0), off[:-1])) * (np.diff(off) > 0)
@@ -254,3 +254,35 @@ def test_learned_frontier_fallback_kernel(setup, monkeypatch):
     off, cells, scores, _ = T.mac_trace(0.6)
     ref, _ = _replay(R, 0.6, tau, 1e30, off, cells, scores)
     _lists_equal(T.lists(0.6), ref)
+
+
+def test_learned_full_size_in_the_bench_configuration():
+    """2^20 Plummer sphere with the shipped network at the operating point the
+    benchmark measures (band theta* - 0.03 .. theta* + 0.25 around theta* =
+    0.5625, tau_pair 3.79e-4, budget 30 tau_pair): the whole call's lists
+    replayed by the oracle bit for bit, and the forces of 300 sampled groups
+    within the gates of the oracle's FP64 evaluation of those lists."""
+    torch = _torch()
+    from paper_1005_5384_amd import learned as L
+    pos, m = W.make("plummer1m")
+    T = og.Tree(pos, m, 16, 64)
+    O = oracle.Tree(pos, m, 16, 64)
+    tau = 3.7855e-4
+    T.set_mac(og.Mlp(L.load_params()), 0.5325, 0.8125, tau, 30 * tau)
+    off, cells, scores, fb = T.mac_trace(0.5625)
+    g = np.repeat(np.arange(off.size - 1, dtype=np.int32), np.diff(off))
+    ref, rfb = O.lists_learned(0.5625, 0.5325, 0.8125, oracle.log10_threshold(tau),
+                               30 * tau, replay=(g, cells, scores))
+    for a, b in zip(T.lists(0.5625), ref):
+        assert np.array_equal(a, b)
+    assert np.array_equal(fb, rfb)
+    acc, pot = T.forces(0.5625, 1e-3)
+    torch.cuda.synchronize()
+    sel = np.random.default_rng(11).choice(O.n_groups, 300, replace=False).astype(np.int32)
+    ar, pr = O.forces_lists(ref, 1e-3, groups=sel)
+    k = ~np.isnan(pr)
+    ea = oracle.rel_err(acc.double().cpu().numpy()[k], ar[k])
+    ep = oracle.rel_err(pot.double().cpu().numpy()[k], pr[k])
+    assert np.median(ea) <= 1e-5 and ea.max() <= 1e-4, (np.median(ea), ea.max())
+    assert np.median(ep) <= 1e-5 and ep.max() <= 1e-4, (np.median(ep), ep.max())
+    T.set_mac(None)

@@ -86,7 +86,7 @@ def test_random_learned_configuration(k):
     T.set_mac(og.Mlp(L.load_params()), lo, hi, tau, budget)
     off, cells, scores, fb = T.mac_trace(theta)
     g = np.repeat(np.arange(off.size - 1, dtype=np.int32), np.diff(off))
-    ref, rfb = O.lists_learned(theta, lo, hi, float(np.float32(np.log10(np.float32(tau)))), budget,
+    ref, rfb = O.lists_learned(theta, lo, hi, oracle.log10_threshold(tau), budget,
                                replay=(g, cells, scores))
     got = T.lists(theta)
     for a, b in zip(got, ref):

@@ -187,3 +187,12 @@ def test_learned_walk_replay_matches_network(small):
         for cc in np.concatenate([c_ids[c_off[gi]:c_off[gi + 1]], l_ids[l_off[gi]:l_off[gi + 1]]]):
             cover[e["topo"][cc, 2]:e["topo"][cc, 2] + e["topo"][cc, 3]] += 1
         assert np.all(cover == 1)
+
+
+def test_log10_threshold_is_the_fp64_logarithm_rounded_once():
+    # exact decades and a power of two: log10 known in closed form
+    assert oracle.log10_threshold(1.0) == 0.0
+    assert oracle.log10_threshold(1e-3) == -3.0  # FP32(1e-3) is within 1e-10 relative of 1e-3
+    assert oracle.log10_threshold(2.0 ** -10) == float(np.float32(-10 * 0.30102999566398120))
+    # the tie that separates it from an FP32 log10: 3.7855e-4 rounds to -3.4218767
+    assert oracle.log10_threshold(3.7855e-4) == float(np.float32(-3.4218767))
