@@ -79,3 +79,26 @@ def test_offset_argument_rules():
         T.forces(0.5, 1e-3, com=True)
     T.set_mac(None)
     T.forces(0.5, 1e-3, com=True, path="fused_wave")
+
+
+@pytest.mark.parametrize("theta", [0.45, 0.57])
+def test_offset_full_size_plummer(theta):
+    """2^20 Plummer sphere at angles the offset test is compared at: the whole
+    call's lists bit-exact, and 300 sampled groups' forces within the gates of
+    the oracle's FP64 evaluation of those lists."""
+    torch = _torch()
+    pos, m = W.make("plummer1m")
+    T = og.Tree(pos, m, 16, 64)
+    O = oracle.Tree(pos, m, 16, 64)
+    ref = O.lists_com(theta, T.export()["mp"][:, :3])
+    for a, b in zip(T.lists(theta, com=True), ref):
+        assert np.array_equal(a, b)
+    acc, pot = T.forces(theta, 1e-3, com=True)
+    torch.cuda.synchronize()
+    sel = np.random.default_rng(17).choice(O.n_groups, 300, replace=False).astype(np.int32)
+    ar, pr = O.forces_lists(ref, 1e-3, groups=sel)
+    k = ~np.isnan(pr)
+    ea = oracle.rel_err(acc.double().cpu().numpy()[k], ar[k])
+    ep = oracle.rel_err(pot.double().cpu().numpy()[k], pr[k])
+    assert np.median(ea) <= 1e-5 and ea.max() <= 1e-4, (np.median(ea), ea.max())
+    assert np.median(ep) <= 1e-5 and ep.max() <= 1e-4, (np.median(ep), ep.max())
