@@ -11,15 +11,16 @@ SOURCES = ["oracle.cpp", "oracle_mac.cpp"]
 OUT = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+def build(verbose: bool = False, src_dir: str = HERE, out: str = OUT) -> str:
+    """Compiles the sources in src_dir (default: this folder) into out."""
+    srcs = [os.path.join(src_dir, s) for s in SOURCES if os.path.exists(os.path.join(src_dir, s))]
     cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-Wall", "-o", OUT + ".tmp"] + srcs
+           "-fPIC", "-shared", "-Wall", "-o", out + ".tmp"] + srcs
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

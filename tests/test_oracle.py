@@ -184,6 +184,7 @@ def test_quadrupole_convergence_slope():
     dirn = np.array([0.48, 0.6, 0.64])
     ds = np.array([4.0, 8.0, 16.0, 32.0])
     errs = {True: [], False: []}
+    perrs = {True: [], False: []}
     for dd in ds:
         tgt = dirn * dd
         ex_a = np.zeros(3)
@@ -196,10 +197,52 @@ def test_quadrupole_convergence_slope():
         for q in (True, False):
             a, p = oracle.multipole_eval(src, ms, tgt, 1e-12, use_quad=q)
             errs[q].append(np.linalg.norm(a - ex_a) / np.linalg.norm(ex_a))
+            perrs[q].append(abs(p - ex_p) / abs(ex_p))
     sq = np.polyfit(np.log(ds), np.log(errs[True]), 1)[0]
     sm = np.polyfit(np.log(ds), np.log(errs[False]), 1)[0]
     assert -3.4 < sq < -2.6, sq
     assert -2.4 < sm < -1.6, sm
+    # the same law for the potential: -M/r - s/(2 r^5) leaves an octupole
+    # error; a wrong sign or factor of the s term leaves the quadrupole's
+    psq = np.polyfit(np.log(ds), np.log(perrs[True]), 1)[0]
+    psm = np.polyfit(np.log(ds), np.log(perrs[False]), 1)[0]
+    assert -3.4 < psq < -2.6, psq
+    assert -2.4 < psm < -1.6, psm
+
+
+def _dumbbell_field(half, m, direction, d):
+    """Monopole + quadrupole field of two masses m at +-half (a 3-vector) seen
+    at distance d along `direction`: the oracle's particle-cell evaluation."""
+    pos = np.array([half, -np.asarray(half)], np.float32)
+    u = np.asarray(direction, np.float64)
+    return oracle.multipole_eval(pos, np.full(2, m, np.float32), u / np.linalg.norm(u) * d, 1e-12)
+
+
+@pytest.mark.parametrize("d", [3.0, 5.0, 12.0])
+def test_dumbbell_multipole_closed_form(d):
+    # Two masses m at +-b from their centre.  The exact potential on the axis
+    # is -m/(d-b) - m/(d+b) = -(2m/d)(1 + b^2/d^2 + b^4/d^4 + ...), off the axis
+    # (perpendicular) -2m/sqrt(d^2+b^2) = -(2m/d)(1 - b^2/(2 d^2) + ...); the
+    # monopole + quadrupole expansion keeps the first two terms of each, and
+    # the accelerations are the radial derivatives of the same series:
+    #   on the axis:    phi = -2m/d - 2 m b^2/d^3,  a_r = -2m/d^2 - 6 m b^2/d^4
+    #   perpendicular:  phi = -2m/d + m b^2/d^3,    a_r = -2m/d^2 + 3 m b^2/d^4
+    # (a_r: the component along the direction from the centre to the target).
+    m = 0.75
+    for half, b2 in (([0.5, 0.0, 0.0], 0.25),           # along x: Q diagonal
+                     ([0.5, 0.5, 0.0], 0.5),            # diagonal: Q_xy != 0
+                     ([0.25, -0.5, 0.5], 0.5625)):      # general: every Q component
+        h = np.asarray(half, np.float64)
+        perp = np.cross(h, [0.3, 0.7, 0.1])
+        for direction, phi_ref, ar_ref in (
+                (h, -2 * m / d - 2 * m * b2 / d ** 3, -2 * m / d ** 2 - 6 * m * b2 / d ** 4),
+                (perp, -2 * m / d + m * b2 / d ** 3, -2 * m / d ** 2 + 3 * m * b2 / d ** 4)):
+            a, phi = _dumbbell_field(half, m, direction, d)
+            u = direction / np.linalg.norm(direction)
+            np.testing.assert_allclose(phi, phi_ref, rtol=1e-12)
+            np.testing.assert_allclose(a @ u, ar_ref, rtol=1e-12)
+            # no tangential component on these two symmetry lines
+            assert np.linalg.norm(a - (a @ u) * u) <= 1e-12 * abs(ar_ref)
 
 
 def test_single_particle_cell_equals_pair():

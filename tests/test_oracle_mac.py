@@ -196,3 +196,68 @@ def test_log10_threshold_is_the_fp64_logarithm_rounded_once():
     assert oracle.log10_threshold(2.0 ** -10) == float(np.float32(-10 * 0.30102999566398120))
     # the tie that separates it from an FP32 log10: 3.7855e-4 rounds to -3.4218767
     assert oracle.log10_threshold(3.7855e-4) == float(np.float32(-3.4218767))
+
+
+def test_features_closed_form_two_pairs():
+    # Four particles with n_leaf = n_group = 2: the root's octant-0 child holds
+    # the pair A (the group), its octant-7 child the pair B (the candidate
+    # cell), both leaves and groups.  Every feature of (A, B) follows from the
+    # geometry by hand:
+    #   B = masses 1 at (5.5, 5.5, 6) and 3 at (6.5, 6.5, 6): tight box side
+    #   l = 1 (extents 1, 1, 0), boundary centre (6, 6, 6), centre of mass
+    #   (6.25, 6.25, 6); a pair's traceless quadrupole is
+    #   mu (3 D D^T - |D|^2 I) with mu = m1 m2 / (m1 + m2) = 3/4 and D = (1, 1, 0),
+    #   so |Q|_F = mu |D|^2 sqrt(6) = 1.5 sqrt(6) (off-diagonal Q_xy = 9/4 carries
+    #   most of it).
+    #   A = masses 2 at (0, 0, 0) and (1, 0.5, 0.25): box extents (1, 0.5, 0.25),
+    #   half-diagonal r_g = sqrt(1.3125) / 2; M_tot = 8, M_B = 4.
+    pos = np.array([[0, 0, 0], [1, 0.5, 0.25], [5.5, 5.5, 6], [6.5, 6.5, 6]], np.float32)
+    m = np.array([2, 2, 1, 3], np.float32)
+    T = oracle.Tree(pos, m, 2, 2)
+    e = T.export()
+    assert T.n_groups == 2 and list(e["groups"]) == [1, 2]
+    assert e["topo"][2, 1] == 0 and list(e["topo"][2, 2:]) == [2, 2]  # B: a leaf of 2
+    f = T.mac_features(np.array([0], np.int32), np.array([2], np.int32))[0].astype(np.float64)
+    l = 1.0
+    gext = np.array([1.0, 0.5, 0.25])
+    d = np.sqrt((6 - 1.0) ** 2 + (6 - 0.5) ** 2 + (6 - 0.25) ** 2)  # centre to the box
+    ref = np.array([
+        d / l,
+        np.log10(4 / 8) / 3,
+        1.5 * np.sqrt(6) / (4 * l * l),
+        np.log2(1 + 0.5 * np.sqrt(1.3125) / l),
+        1.0, 1.0, 0.0,
+        *np.log2(1 + gext / l),
+        np.log2(1 + 1) / np.log2(22),                      # B sits at depth 1
+        np.sqrt(2 * 0.25 ** 2) / l,                        # |com - boundary centre| / l
+    ])
+    np.testing.assert_allclose(f, ref, rtol=2e-6, atol=1e-7)
+
+
+def test_forward_single_paths_closed_form():
+    # Two paths through an otherwise zero network, weights and inputs exact in
+    # BF16: y = w3[a] relu(W2[a, b] h_b + W2[a, c] h_c + b2[a]) + b3 with
+    # h_b = relu(W1[b, k] x_k + b1[b]), h_c = relu(W1[c, j] x_j + b1[c]).  A
+    # transposed W1 or W2 reads other (zero) entries and gives b3 + w3 relu(b2).
+    a, b, c, k, j = 5, 17, 40, 3, 11
+    P = np.zeros(NP)
+    P[b * 12 + k] = 1.5                # W1[b, k]
+    P[c * 12 + j] = -0.75              # W1[c, j]
+    P[768 + b] = 0.25                  # b1[b]
+    P[768 + c] = 1.0                   # b1[c]
+    P[832 + a * 64 + b] = -2.0         # W2[a, b]
+    P[832 + a * 64 + c] = 0.5          # W2[a, c]
+    P[4928 + a] = 4.0                  # b2[a]
+    P[4992 + a] = 0.5                  # w3[a]
+    P[5056] = 0.125                    # b3
+    x = np.zeros((64, 12), np.float32)
+    i = np.arange(64)
+    x[:, k] = (i % 16) / 4 - 2         # multiples of 1/4: every value below has at most
+    x[:, j] = 1 - (i // 4) / 4         # 8 significant bits, so BF16 rounding is exact
+    hb = np.maximum(1.5 * x[:, k] + 0.25, 0)
+    hc = np.maximum(-0.75 * x[:, j] + 1.0, 0)
+    ref = 0.5 * np.maximum(-2.0 * hb + 0.5 * hc + 4.0, 0) + 0.125
+    for rnd in (False, True):
+        y = oracle.mlp_forward(P, x, round_bf16=rnd)
+        np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12)
+    assert np.ptp(ref) > 1.0
