@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libocgrav.so")
+# OCTGRAV_LIB selects another build of the same sources (the sanitizer build
+# that the CPU checks of the host code load).
+LIB_PATH = os.environ.get("OCTGRAV_LIB") or os.path.join(HERE, "libocgrav.so")
 
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY = 0, -1, -2, -3, -4
 BUILD_HOST_ONLY = 1
