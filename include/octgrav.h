@@ -242,6 +242,15 @@ int octgrav_mlp_set_stream(octgrav_mlp* m, void* hip_stream);
 /* Replaces the parameters (host, 5057 FP32, finite) and zeroes the moments. */
 int octgrav_mlp_set_params(octgrav_mlp* m, const float* params);
 int octgrav_mlp_get_params(const octgrav_mlp* m, float* params);
+/* Training checkpoints: the Adam first and second moments (host, 5057 FP32
+ * each), and the whole optimiser state restored at once (parameters and
+ * moments, host, 5057 FP32 each; all finite, second moments >= 0, else
+ * OCTGRAV_EINVAL and nothing changes).  With the step count kept by the
+ * caller, a restored network continues training exactly as the saved one
+ * would have.  Synchronous. */
+int octgrav_mlp_get_moments(const octgrav_mlp* m, float* mom1, float* mom2);
+int octgrav_mlp_set_state(octgrav_mlp* m, const float* params, const float* mom1,
+                          const float* mom2);
 /* y[b] (device FP32) for inputs x (device, b x 12 FP32).  Synchronous. */
 int octgrav_mlp_forward(octgrav_mlp* m, const float* x, int64_t b, float* y);
 /*
@@ -310,7 +319,13 @@ void octgrav_sim_free(octgrav_sim* s); /* NULL-safe */
 int octgrav_sim_set_stream(octgrav_sim* s, void* hip_stream);
 /* steps leapfrog steps of length dt with opening angle theta and softening
  * eps (forces at the current positions are computed first when missing or
- * when theta / eps changed; steps = 0 only does that).  Synchronous. */
+ * when theta / eps changed; steps = 0 only does that).  Synchronous.
+ * A failure inside a step (after its first half-kick: the rebuild or the
+ * forces fail, or a device error) leaves velocities, positions and
+ * accelerations at different times; the handle is then marked inconsistent
+ * and every later octgrav_sim_run, octgrav_sim_energy and octgrav_sim_state
+ * returns OCTGRAV_EINVAL (free it and create a new one from saved state).
+ * A failure before the first step (the initial forces) changes nothing. */
 int octgrav_sim_run(octgrav_sim* s, float theta, float eps, float dt, int32_t steps);
 /* out = {K, W, E = K + W, sum m vx, sum m vy, sum m vz} in FP64: K = 1/2 sum
  * m v^2, W = 1/2 sum m phi with the last forces (potentials self-excluded). */

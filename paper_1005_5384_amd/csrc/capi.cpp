@@ -1039,6 +1039,34 @@ int octgrav_mlp_set_params(octgrav_mlp* m, const float* params) {
   return OCTGRAV_OK;
 }
 
+int octgrav_mlp_set_state(octgrav_mlp* m, const float* params, const float* mom1,
+                          const float* mom2) {
+  g_err.clear();
+  if (!m || !params || !mom1 || !mom2) return fail(OCTGRAV_EINVAL, "NULL argument");
+  for (int i = 0; i < kMlpParams; ++i)
+    if (!std::isfinite(params[i]) || !std::isfinite(mom1[i]) || !std::isfinite(mom2[i]) ||
+        mom2[i] < 0.0f)
+      return fail(OCTGRAV_EINVAL, "non-finite parameter or moment, or negative second moment");
+  if (hipMemcpy(m->P, params, kMlpParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->mom1, mom1, kMlpParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->mom2, mom2, kMlpParams * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "state upload failed");
+  if (launch_mlp_pack((const float*)m->P, m->pk, m->stream) ||
+      hipStreamSynchronize(m->stream) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "pack failed");
+  return OCTGRAV_OK;
+}
+
+int octgrav_mlp_get_moments(const octgrav_mlp* m, float* mom1, float* mom2) {
+  g_err.clear();
+  if (!m || !mom1 || !mom2) return fail(OCTGRAV_EINVAL, "NULL argument");
+  if (hipStreamSynchronize(m->stream) != hipSuccess ||
+      hipMemcpy(mom1, m->mom1, kMlpParams * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(mom2, m->mom2, kMlpParams * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "moment copy-back failed");
+  return OCTGRAV_OK;
+}
+
 int octgrav_mlp_get_params(const octgrav_mlp* m, float* params) {
   g_err.clear();
   if (!m || !params) return fail(OCTGRAV_EINVAL, "NULL argument");
@@ -1106,6 +1134,10 @@ struct octgrav_sim {
   double *kpart = nullptr, *kout = nullptr;
   octgrav_tree* tree = nullptr;
   bool have_forces = false;
+  // Set when a run fails after a step's first half-kick: velocities, positions
+  // and accelerations no longer belong to one time, so the handle refuses
+  // further runs, energies and states.
+  bool broken = false;
   float theta = -1.0f, eps = -1.0f;
   double timings[3] = {0, 0, 0};  // last run: ms per step, of which tree build, forces
 
@@ -1197,9 +1229,15 @@ int octgrav_sim_set_stream(octgrav_sim* s, void* hip_stream) {
   return OCTGRAV_OK;
 }
 
+static int sim_broken() {
+  return fail(OCTGRAV_EINVAL,
+              "an earlier run failed in the middle of a step; the state is inconsistent");
+}
+
 int octgrav_sim_run(octgrav_sim* s, float theta, float eps, float dt, int32_t steps) {
   g_err.clear();
   if (!s) return fail(OCTGRAV_EINVAL, "NULL handle");
+  if (s->broken) return sim_broken();
   if (!(theta >= 0.0f && theta <= 1.0f)) return fail(OCTGRAV_EINVAL, "theta must be in [0, 1]");
   if (!(eps > 0.0f) || !std::isfinite(eps)) return fail(OCTGRAV_EINVAL, "eps must be finite and > 0");
   if (!std::isfinite(dt) || steps < 0) return fail(OCTGRAV_EINVAL, "bad dt or steps");
@@ -1214,15 +1252,20 @@ int octgrav_sim_run(octgrav_sim* s, float theta, float eps, float dt, int32_t st
       t0 = std::chrono::steady_clock::now();
     }
     for (int32_t k = 0; k < steps; ++k) {
+      // From the first half-kick on, a failure leaves the step half done.
+      s->broken = true;
       if (launch_kick(s->vel, s->acc, s->n, 0.5f * dt, s->stream) ||
           launch_drift(s->pos, s->vel, s->n, dt, s->stream))
         return fail(OCTGRAV_EHIP, "leapfrog launch failed");
       if (int rc = s->rebuild_and_force(&tb, &tf)) return rc;
       if (launch_kick(s->vel, s->acc, s->n, 0.5f * dt, s->stream))
         return fail(OCTGRAV_EHIP, "leapfrog launch failed");
+      s->broken = false;
     }
-    if (hipStreamSynchronize(s->stream) != hipSuccess)
+    if (hipStreamSynchronize(s->stream) != hipSuccess) {
+      s->broken = steps > 0;
       return fail(OCTGRAV_EHIP, "device error during integration");
+    }
     if (steps > 0) {
       const double ms = std::chrono::duration<double, std::milli>(
                             std::chrono::steady_clock::now() - t0).count();
@@ -1239,6 +1282,7 @@ int octgrav_sim_run(octgrav_sim* s, float theta, float eps, float dt, int32_t st
 int octgrav_sim_energy(octgrav_sim* s, double out[6]) {
   g_err.clear();
   if (!s || !out) return fail(OCTGRAV_EINVAL, "NULL argument");
+  if (s->broken) return sim_broken();
   if (!s->have_forces) return fail(OCTGRAV_EINVAL, "no forces yet: run at least once (steps may be 0)");
   double k4[4], mom[3], w;
   if (launch_kinetic(s->mass, s->vel, s->n, s->kpart, s->kout, s->stream) ||
@@ -1257,6 +1301,7 @@ int octgrav_sim_energy(octgrav_sim* s, double out[6]) {
 
 int octgrav_sim_state(const octgrav_sim* s, float* pos, float* vel, float* acc) {
   if (!s) return fail(OCTGRAV_EINVAL, "NULL handle");
+  if (s->broken) return sim_broken();
   if (hipStreamSynchronize(s->stream) != hipSuccess ||
       (pos && hipMemcpy(pos, s->pos, s->n * 12, hipMemcpyDeviceToHost) != hipSuccess) ||
       (vel && hipMemcpy(vel, s->vel, s->n * 12, hipMemcpyDeviceToHost) != hipSuccess) ||

@@ -54,18 +54,103 @@ def init_params(seed: int) -> np.ndarray:
     return P
 
 
+# ------------------------------------------------------------------ checkpoints
+#
+# A training checkpoint is an .npz of plain arrays (no pickled objects):
+# format version, FP32 master parameters, Adam moments, the Adam step count,
+# the epochs done, the batch generator's state, the run's settings and a
+# SHA-256 over all of them.  Loading checks the version, the shapes and the
+# checksum; a resumed run continues exactly as the uninterrupted one.
+
+CKPT_VERSION = 1
+CKPT_KEYS = ("version", "params", "mom1", "mom2", "step", "epoch", "gen_state", "settings")
+
+
+def _ckpt_digest(arrs) -> np.ndarray:
+    import hashlib
+    h = hashlib.sha256()
+    for k in CKPT_KEYS:
+        a = np.ascontiguousarray(arrs[k])
+        h.update(k.encode())
+        h.update(str(a.dtype).encode())
+        h.update(np.asarray(a.shape, np.int64).tobytes())
+        h.update(a.tobytes())
+    return np.frombuffer(h.digest(), np.uint8).copy()
+
+
+def pack_checkpoint(params, mom1, mom2, step, epoch, gen_state, settings) -> dict:
+    """The arrays of a checkpoint (settings: [epochs, batch, lr, lr_final,
+    tau, seed] as FP64)."""
+    arrs = {
+        "version": np.int64(CKPT_VERSION),
+        "params": np.ascontiguousarray(params, np.float32),
+        "mom1": np.ascontiguousarray(mom1, np.float32),
+        "mom2": np.ascontiguousarray(mom2, np.float32),
+        "step": np.int64(step),
+        "epoch": np.int64(epoch),
+        "gen_state": np.ascontiguousarray(gen_state, np.uint8),
+        "settings": np.ascontiguousarray(settings, np.float64),
+    }
+    for k in ("params", "mom1", "mom2"):
+        if arrs[k].shape != (og.N_PARAMS,):
+            raise ValueError(f"checkpoint {k}: expected {og.N_PARAMS} values")
+    arrs["sha256"] = _ckpt_digest(arrs)
+    return arrs
+
+
+def save_checkpoint(path, arrs) -> None:
+    """Writes the checkpoint atomically (temporary file, then rename)."""
+    tmp = path + ".tmp.npz"
+    with open(tmp, "wb") as f:
+        np.savez(f, **arrs)
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path) -> dict:
+    """Reads and verifies a checkpoint; ValueError if it is of another
+    version, malformed or corrupted."""
+    with np.load(path, allow_pickle=False) as z:
+        missing = [k for k in CKPT_KEYS + ("sha256",) if k not in z.files]
+        if missing:
+            raise ValueError(f"{path}: not a training checkpoint (missing {missing})")
+        arrs = {k: z[k] for k in CKPT_KEYS + ("sha256",)}
+    if int(arrs["version"]) != CKPT_VERSION:
+        raise ValueError(f"{path}: checkpoint version {int(arrs['version'])}, "
+                         f"this code reads {CKPT_VERSION}")
+    for k in ("params", "mom1", "mom2"):
+        if arrs[k].dtype != np.float32 or arrs[k].shape != (og.N_PARAMS,):
+            raise ValueError(f"{path}: {k} has the wrong type or shape")
+    if not np.array_equal(arrs["sha256"], _ckpt_digest(arrs)):
+        raise ValueError(f"{path}: checksum mismatch (corrupted checkpoint)")
+    return arrs
+
+
 def train(x, y, epochs=30, batch=4096, lr=1e-3, tau=PINBALL_TAU, seed=0, params=None,
-          lr_final=1e-4, log=None):
+          lr_final=1e-4, log=None, checkpoint=None, resume=None, stop_after=None):
     """Trains a network on (x, y) (CUDA tensors) with mini-batch Adam and a
-    geometric learning-rate decay; returns the Mlp."""
+    geometric learning-rate decay; returns the Mlp.  With `checkpoint`, the
+    optimiser state is saved there after every epoch; with `resume`, training
+    continues from that checkpoint (same data and settings required);
+    `stop_after` ends the run after that many epochs in all."""
     import torch
+    settings = np.array([epochs, batch, lr, lr_final, tau, seed], np.float64)
     m = og.Mlp(init_params(seed) if params is None else params)
     n = x.shape[0]
     gen = torch.Generator().manual_seed(seed)
     nb = max(1, n // batch)
     total = epochs * nb
-    step = 0
-    for ep in range(epochs):
+    step, ep0 = 0, 0
+    if resume is not None:
+        ck = load_checkpoint(resume)
+        if not np.array_equal(ck["settings"], settings):
+            raise ValueError(f"{resume}: saved with other settings {ck['settings'].tolist()}")
+        m.set_state(ck["params"], ck["mom1"], ck["mom2"])
+        gen.set_state(torch.from_numpy(ck["gen_state"].copy()))
+        step, ep0 = int(ck["step"]), int(ck["epoch"])
+        if step != ep0 * nb:
+            raise ValueError(f"{resume}: step {step} does not match {ep0} epochs of {nb} batches")
+    last = epochs if stop_after is None else min(epochs, stop_after)
+    for ep in range(ep0, last):
         perm = torch.randperm(n, generator=gen).cuda()
         run = 0.0
         for b in range(nb):
@@ -76,6 +161,10 @@ def train(x, y, epochs=30, batch=4096, lr=1e-3, tau=PINBALL_TAU, seed=0, params=
             m.adam(step, lr=lr * (lr_final / lr) ** (step / total))
         if log:
             log(f"epoch {ep + 1}/{epochs} loss {run / nb:.5f}")
+        if checkpoint is not None:
+            m1, m2 = m.moments()
+            save_checkpoint(checkpoint, pack_checkpoint(m.params(), m1, m2, step, ep + 1,
+                                                        gen.get_state().numpy(), settings))
     return m
 
 
@@ -157,11 +246,15 @@ def main():
     tr.add_argument("--seed", type=int, default=0)
     tr.add_argument("--merger", action="store_true",
                     help="add the snapshots of a two-Plummer merger run to the static sets")
+    tr.add_argument("--checkpoint", default=None,
+                    help="save the optimiser state here after every epoch")
+    tr.add_argument("--resume", default=None, help="continue from this checkpoint")
     a = ap.parse_args()
     if a.cmd == "train":
         x, y = training_data(a.stride, log=lambda s: print(s, flush=True), merger=a.merger)
         t0 = time.time()
-        m = train(x, y, epochs=a.epochs, seed=a.seed, log=lambda s: print(s, flush=True))
+        m = train(x, y, epochs=a.epochs, seed=a.seed, log=lambda s: print(s, flush=True),
+                  checkpoint=a.checkpoint, resume=a.resume)
         print(f"trained on {x.shape[0]} pairs in {time.time() - t0:.1f} s", flush=True)
         np.save(a.out, m.params())
 

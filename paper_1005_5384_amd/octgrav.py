@@ -53,6 +53,7 @@ EXPORTED = ["octgrav_build_tree", "octgrav_build_tree_ex", "octgrav_forces", "oc
             "octgrav_last_counts", "octgrav_direct", "octgrav_mac_collect",
             "octgrav_last_timings", "octgrav_mlp_create", "octgrav_mlp_free",
             "octgrav_mlp_set_stream", "octgrav_mlp_set_params", "octgrav_mlp_get_params",
+            "octgrav_mlp_get_moments", "octgrav_mlp_set_state",
             "octgrav_mlp_forward", "octgrav_mlp_loss_grad", "octgrav_mlp_adam", "octgrav_set_mac",
             "octgrav_mac_stats", "octgrav_mac_trace", "octgrav_sim_create", "octgrav_sim_free",
             "octgrav_sim_set_stream", "octgrav_sim_run", "octgrav_sim_energy", "octgrav_sim_state",
@@ -102,6 +103,8 @@ def lib():
         L.octgrav_mlp_set_stream.argtypes = [vp, vp]
         L.octgrav_mlp_set_params.argtypes = [vp, vp]
         L.octgrav_mlp_get_params.argtypes = [vp, vp]
+        L.octgrav_mlp_get_moments.argtypes = [vp, vp, vp]
+        L.octgrav_mlp_set_state.argtypes = [vp, vp, vp, vp]
         L.octgrav_mlp_forward.argtypes = [vp, vp, i64, vp]
         L.octgrav_mlp_loss_grad.argtypes = [vp, vp, vp, i64, f32, vp, vp]
         L.octgrav_mlp_adam.argtypes = [vp, f32, f32, f32, f32, i32]
@@ -336,6 +339,22 @@ class Mlp:
         self._bind_stream()
         _check(lib().octgrav_mlp_get_params(self._h, _ptr(p)))
         return p
+
+    def moments(self):
+        """Adam's (first, second) moments, [5057] FP32 each."""
+        m1 = np.zeros(N_PARAMS, np.float32)
+        m2 = np.zeros(N_PARAMS, np.float32)
+        self._bind_stream()
+        _check(lib().octgrav_mlp_get_moments(self._h, _ptr(m1), _ptr(m2)))
+        return m1, m2
+
+    def set_state(self, params, mom1, mom2):
+        """Restores parameters and Adam moments (a training checkpoint)."""
+        a = [np.ascontiguousarray(v, dtype=np.float32) for v in (params, mom1, mom2)]
+        if any(v.size != N_PARAMS for v in a):
+            raise ValueError(f"need {N_PARAMS} values each")
+        self._bind_stream()
+        _check(lib().octgrav_mlp_set_state(self._h, *(_ptr(v) for v in a)))
 
     def forward(self, x):
         """x: float32 CUDA tensor [b, 12] -> y [b]."""

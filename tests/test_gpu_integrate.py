@@ -67,6 +67,30 @@ def test_sim_argument_checks():
         og.Sim(pos, vel, m)
 
 
+def test_failed_step_leaves_the_handle_refusing(monkeypatch):
+    """A rebuild that fails inside a step (injected allocation failure) marks
+    the handle inconsistent: later runs, energies and states are refused.  A
+    failure of the initial forces changes nothing."""
+    _torch()
+    pos, vel, m = W.plummer_with_velocities(2048, 14)
+    S = og.Sim(pos, vel, m)
+    monkeypatch.setenv("OCTGRAV_FAIL_ALLOC", "1")
+    with pytest.raises(og.OctgravError):
+        S.run(0.5, 0.01, 1.0 / 256, 0)   # initial forces fail: nothing moved
+    monkeypatch.delenv("OCTGRAV_FAIL_ALLOC")
+    S.run(0.5, 0.01, 1.0 / 256, 2)
+    p0, v0, _ = S.state()
+    assert np.isfinite(S.energy()["E"])
+    monkeypatch.setenv("OCTGRAV_FAIL_ALLOC", "1")
+    with pytest.raises(og.OctgravError, match="allocation"):
+        S.run(0.5, 0.01, 1.0 / 256, 1)   # the rebuild of the step fails
+    monkeypatch.delenv("OCTGRAV_FAIL_ALLOC")
+    for call in (lambda: S.run(0.5, 0.01, 1.0 / 256, 1), S.energy, S.state):
+        with pytest.raises(og.OctgravError, match="inconsistent"):
+            call()
+    S.close()
+
+
 def test_rebuilt_tree_matches_a_fresh_tree_after_collapse():
     """A cold sphere collapses, so the tree changes shape from step to step
     and the reused device buffers grow; the forces of the last rebuild equal

@@ -120,6 +120,32 @@ def test_training_reduces_loss():
     assert l1 < 0.3 * l0, (l0, l1)
 
 
+def test_training_resumed_from_checkpoint_equals_uninterrupted(tmp_path):
+    """Two epochs, a checkpoint, a fresh network resumed from it for two more:
+    parameters and Adam moments equal those of four uninterrupted epochs, bit
+    for bit (the kernels and the batch order are deterministic)."""
+    torch = _torch()
+    from paper_1005_5384_amd import learned as L
+    rng = np.random.default_rng(6)
+    x = rng.normal(0, 1, (6000, 12)).astype(np.float32)
+    t = (-3 + x[:, 0] - 0.5 * x[:, 1] ** 2).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    kw = dict(epochs=4, batch=1024, lr=3e-3, lr_final=3e-4, seed=7)
+    full = L.train(xd, td, **kw)
+    ck = str(tmp_path / "train.npz")
+    L.train(xd, td, checkpoint=ck, stop_after=2, **kw)
+    saved = L.load_checkpoint(ck)
+    assert int(saved["epoch"]) == 2 and int(saved["step"]) == 2 * (6000 // 1024)
+    resumed = L.train(xd, td, resume=ck, **kw)
+    assert np.array_equal(full.params(), resumed.params())
+    for a, b in zip(full.moments(), resumed.moments()):
+        assert np.array_equal(a, b)
+    # the resumed network differs from the two-epoch one (training went on)
+    assert not np.array_equal(saved["params"], resumed.params())
+    with pytest.raises(ValueError, match="settings"):
+        L.train(xd, td, resume=ck, **dict(kw, lr=1e-3))
+
+
 # ---------------------------------------------------------------- learned walk
 
 @pytest.fixture(scope="module")
