@@ -68,6 +68,11 @@ def lib():
         L.orc_lists_learned.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float,
                                         vp, vp, vp, vp, C.c_int64, vp, vp, vp, vp,
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
+        L.orc_lists_groups.argtypes = [vp, C.c_float, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+        L.orc_lists_learned_groups.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float,
+                                               C.c_float, vp, vp, vp, vp, C.c_int64, vp,
+                                               C.c_int64, vp, vp, vp, vp, C.POINTER(C.c_int64),
+                                               C.POINTER(C.c_int64), vp]
         _lib = L
     return _lib
 
@@ -167,20 +172,27 @@ class Tree:
         lib().orc_tree_cubes(self._h, out)
         return out
 
-    def _lists(self, fn, theta):
+    def _lists(self, fn, theta, ng=None):
+        ng = self.n_groups if ng is None else ng
         nc, nl = C.c_int64(), C.c_int64()
-        fn(self._h, float(theta), None, None, None, None, C.byref(nc), C.byref(nl))
-        c_off = np.zeros(self.n_groups + 1, np.int64)
-        l_off = np.zeros(self.n_groups + 1, np.int64)
+        if fn(self._h, float(theta), None, None, None, None, C.byref(nc), C.byref(nl)) != 0:
+            raise ValueError("oracle lists rejected their arguments")
+        c_off = np.zeros(ng + 1, np.int64)
+        l_off = np.zeros(ng + 1, np.int64)
         c_ids = np.zeros(max(1, nc.value), np.int32)
         l_ids = np.zeros(max(1, nl.value), np.int32)
         fn(self._h, float(theta), _ptr(c_off), _ptr(c_ids), _ptr(l_off), _ptr(l_ids),
            C.byref(nc), C.byref(nl))
         return c_off, c_ids[:nc.value], l_off, l_ids[:nl.value]
 
-    def lists(self, theta):
-        """(c_off, c_ids, l_off, l_ids): CSR lists per group from the stack walk."""
-        return self._lists(lib().orc_lists, theta)
+    def lists(self, theta, groups=None):
+        """(c_off, c_ids, l_off, l_ids): CSR lists per group from the stack walk
+        (of the given group indices only, in that order, with `groups`)."""
+        if groups is None:
+            return self._lists(lib().orc_lists, theta)
+        sel = np.ascontiguousarray(groups, np.int32)
+        fn = lambda h, th, *a: lib().orc_lists_groups(h, th, _ptr(sel), sel.size, *a)
+        return self._lists(fn, theta, sel.size)
 
     def lists_brute(self, theta):
         """The same lists from their walk-free characterisation (slow)."""
@@ -228,9 +240,10 @@ class Tree:
         return out
 
     def lists_learned(self, theta, theta_lo, theta_hi, log10_tau, budget, params=None,
-                      replay=None):
+                      replay=None, groups=None):
         """Lists under the learned criterion (network `params`, or a replay
-        (g, c, score) table sorted by (g, c)); returns lists + fell_back."""
+        (g, c, score) table sorted by (g, c)); returns lists + fell_back
+        (of the given group indices only, in that order, with `groups`)."""
         P = None if params is None else np.ascontiguousarray(params, np.float64)
         if replay is not None:
             rg, rc, rs = (np.ascontiguousarray(replay[0], np.int32),
@@ -243,16 +256,24 @@ class Tree:
         nc, nl = C.c_int64(), C.c_int64()
         args = (self._h, float(theta), float(theta_lo), float(theta_hi), float(log10_tau),
                 float(budget), _ptr(P), _ptr(rg), _ptr(rc), _ptr(rs), nr)
-        rc_ = lib().orc_lists_learned(*args, None, None, None, None, C.byref(nc), C.byref(nl), None)
-        if rc_ != 0:
+        if groups is None:
+            fn, ng = lib().orc_lists_learned, self.n_groups
+        else:
+            sel = np.ascontiguousarray(groups, np.int32)
+            args = args + (_ptr(sel), sel.size)
+            fn, ng = lib().orc_lists_learned_groups, sel.size
+        rc_ = fn(*args, None, None, None, None, C.byref(nc), C.byref(nl), None)
+        if rc_ == -2:
             raise ValueError("replay table misses a band candidate")
-        c_off = np.zeros(self.n_groups + 1, np.int64)
-        l_off = np.zeros(self.n_groups + 1, np.int64)
+        if rc_ != 0:
+            raise ValueError("oracle learned lists rejected their arguments")
+        c_off = np.zeros(ng + 1, np.int64)
+        l_off = np.zeros(ng + 1, np.int64)
         c_ids = np.zeros(max(1, nc.value), np.int32)
         l_ids = np.zeros(max(1, nl.value), np.int32)
-        fb = np.zeros(self.n_groups, np.int32)
-        lib().orc_lists_learned(*args, _ptr(c_off), _ptr(c_ids), _ptr(l_off), _ptr(l_ids),
-                                C.byref(nc), C.byref(nl), _ptr(fb))
+        fb = np.zeros(ng, np.int32)
+        fn(*args, _ptr(c_off), _ptr(c_ids), _ptr(l_off), _ptr(l_ids), C.byref(nc), C.byref(nl),
+           _ptr(fb))
         return (c_off, c_ids[:nc.value], l_off, l_ids[:nl.value]), fb
 
     def forces(self, theta, eps, groups=None):

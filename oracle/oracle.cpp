@@ -315,12 +315,19 @@ void brute_group(const Tree& t, int32_t gcell, float theta, std::vector<int32_t>
 
 typedef void (*walk_fn)(const Tree&, int32_t, float, std::vector<int32_t>&, std::vector<int32_t>&);
 
+// CSR lists of the selected groups (sel: group indices, NULL = every group
+// in order), in the order given.
 int lists_impl(const Tree& t, float theta, walk_fn fn, int64_t* c_off, int32_t* c_ids,
-               int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
-  int64_t ng = (int64_t)t.groups.size();
+               int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l,
+               const int32_t* sel = nullptr, int64_t n_sel = -1) {
+  const int64_t ngt = (int64_t)t.groups.size();
+  if (sel)
+    for (int64_t u = 0; u < n_sel; ++u)
+      if (sel[u] < 0 || sel[u] >= ngt) return -1;
+  const int64_t ng = sel ? n_sel : ngt;
   std::vector<std::vector<int32_t>> C(ng), Lv(ng);
 #pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t g = 0; g < ng; ++g) fn(t, t.groups[g], theta, C[g], Lv[g]);
+  for (int64_t g = 0; g < ng; ++g) fn(t, t.groups[sel ? sel[g] : g], theta, C[g], Lv[g]);
   int64_t sc = 0, sl = 0;
   for (int64_t g = 0; g < ng; ++g) {
     if (c_off) c_off[g] = sc;
@@ -615,6 +622,15 @@ int orc_mac_open(const float* gmin, const float* gmax, const float* geo, float t
 int orc_lists(const void* h, float theta, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
               int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
   return lists_impl(*(const Tree*)h, theta, walk_group, c_off, c_ids, l_off, l_ids, n_c, n_l);
+}
+
+// The lists of the n_sel groups sel (group indices), CSR in that order
+// (c_off, l_off have n_sel + 1 entries).  -1 if an index is out of range.
+int orc_lists_groups(const void* h, float theta, const int32_t* sel, int64_t n_sel, int64_t* c_off,
+                     int32_t* c_ids, int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
+  if (!sel || n_sel < 0) return -1;
+  return lists_impl(*(const Tree*)h, theta, walk_group, c_off, c_ids, l_off, l_ids, n_c, n_l, sel,
+                    n_sel);
 }
 
 int orc_lists_brute(const void* h, float theta, int64_t* c_off, int32_t* c_ids, int64_t* l_off,

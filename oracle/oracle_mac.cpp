@@ -332,26 +332,34 @@ int orc_adam(double* P, double* m, double* v, const double* g, int64_t n, double
   return 0;
 }
 
-// Lists of every group under the learned criterion.  Scores come from the
-// network P (BF16 mirror) or, when P == NULL, from a replay table of
-// (group index, cell id, score) triples sorted by (group, cell).  fell_back
-// [ng] (may be NULL) receives 1 for groups that fell back to theta.
-int orc_lists_learned(const void* h, float theta, float th_lo, float th_hi, float log10_tau,
-                      float budget, const double* P, const int32_t* rg, const int32_t* rc,
-                      const float* rs, int64_t nr, int64_t* c_off, int32_t* c_ids,
-                      int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l,
-                      int32_t* fell_back) {
-  const Tree& t = *(const Tree*)h;
-  const int64_t ng = (int64_t)t.groups.size();
+// Lists under the learned criterion of the selected groups (sel: group
+// indices, NULL = every group in order), CSR in the order given.  Scores
+// come from the network P (BF16 mirror) or, when P == NULL, from a replay
+// table of (group index, cell id, score) triples sorted by (group, cell).
+// fell_back (one per selected group, may be NULL) receives 1 for groups that
+// fell back to theta.
+static int learned_impl(const Tree& t, float theta, float th_lo, float th_hi, float log10_tau,
+                        float budget, const double* P, const int32_t* rg, const int32_t* rc,
+                        const float* rs, int64_t nr, int64_t* c_off, int32_t* c_ids,
+                        int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l,
+                        int32_t* fell_back, const int32_t* sel, int64_t n_sel) {
+  const int64_t ngt = (int64_t)t.groups.size();
+  if (sel)
+    for (int64_t u = 0; u < n_sel; ++u)
+      if (sel[u] < 0 || sel[u] >= ngt) return -1;
+  for (int64_t k = 0; k < nr; ++k)
+    if (rg[k] < 0 || rg[k] >= ngt) return -1;
+  const int64_t ng = sel ? n_sel : ngt;
   std::vector<std::vector<int32_t>> C(ng), Lv(ng);
-  std::vector<int64_t> rbeg(ng + 1, nr);
+  std::vector<int64_t> rbeg(ngt + 1, nr);
   if (!P) {  // index the replay table by group
     for (int64_t k = nr - 1; k >= 0; --k) rbeg[rg[k]] = k;
-    for (int64_t u = ng - 1; u >= 0; --u) rbeg[u] = std::min(rbeg[u], rbeg[u + 1]);
+    for (int64_t u = ngt - 1; u >= 0; --u) rbeg[u] = std::min(rbeg[u], rbeg[u + 1]);
   }
   int bad = 0;
 #pragma omp parallel for schedule(dynamic, 8) reduction(| : bad)
-  for (int64_t u = 0; u < ng; ++u) {
+  for (int64_t v = 0; v < ng; ++v) {
+    const int64_t u = sel ? sel[v] : v;
     const int32_t gc = t.groups[u];
     auto score = [&](int32_t c) -> float {
       if (P) {
@@ -370,8 +378,8 @@ int orc_lists_learned(const void* h, float theta, float th_lo, float th_hi, floa
       }
       return rs[it - rc];
     };
-    const bool fb = walk_learned(t, gc, theta, th_lo, th_hi, log10_tau, budget, score, C[u], Lv[u]);
-    if (fell_back) fell_back[u] = fb ? 1 : 0;
+    const bool fb = walk_learned(t, gc, theta, th_lo, th_hi, log10_tau, budget, score, C[v], Lv[v]);
+    if (fell_back) fell_back[v] = fb ? 1 : 0;
   }
   if (bad) return -2;  // a band candidate without a replayed score
   int64_t sc = 0, sl = 0;
@@ -388,6 +396,28 @@ int orc_lists_learned(const void* h, float theta, float th_lo, float th_hi, floa
   if (n_c) *n_c = sc;
   if (n_l) *n_l = sl;
   return 0;
+}
+
+// Lists of every group under the learned criterion (see learned_impl).
+int orc_lists_learned(const void* h, float theta, float th_lo, float th_hi, float log10_tau,
+                      float budget, const double* P, const int32_t* rg, const int32_t* rc,
+                      const float* rs, int64_t nr, int64_t* c_off, int32_t* c_ids,
+                      int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l,
+                      int32_t* fell_back) {
+  return learned_impl(*(const Tree*)h, theta, th_lo, th_hi, log10_tau, budget, P, rg, rc, rs, nr,
+                      c_off, c_ids, l_off, l_ids, n_c, n_l, fell_back, nullptr, -1);
+}
+
+// The same for the n_sel groups sel (group indices; the replay table's
+// group column holds group indices too).
+int orc_lists_learned_groups(const void* h, float theta, float th_lo, float th_hi,
+                             float log10_tau, float budget, const double* P, const int32_t* rg,
+                             const int32_t* rc, const float* rs, int64_t nr, const int32_t* sel,
+                             int64_t n_sel, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
+                             int32_t* l_ids, int64_t* n_c, int64_t* n_l, int32_t* fell_back) {
+  if (!sel || n_sel < 0) return -1;
+  return learned_impl(*(const Tree*)h, theta, th_lo, th_hi, log10_tau, budget, P, rg, rc, rs, nr,
+                      c_off, c_ids, l_off, l_ids, n_c, n_l, fell_back, sel, n_sel);
 }
 
 }  // extern "C"

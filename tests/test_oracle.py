@@ -403,3 +403,31 @@ def test_forces_from_given_lists_equal_own_walk():
     c, _ = T.forces_lists(T.lists(0.4), 0.01)
     d, _ = T.forces(0.4, 0.01)
     assert np.array_equal(c, d)
+
+
+def test_lists_of_selected_groups_equal_full_lists():
+    # the group-selected walk (used where full lists would not fit in host
+    # memory) gives exactly the full walk's lists of those groups, in the
+    # order asked for, also under the learned criterion; bad indices rejected
+    pos, m = W.plummer(20000, 5)
+    O = oracle.Tree(pos, m, 16, 64)
+    sel = np.array([3, 0, 17, O.n_groups - 1, 3], np.int32)
+    for theta in (0.3, 0.6):
+        full = O.lists(theta)
+        part = O.lists(theta, groups=sel)
+        for j, g in enumerate(sel):
+            for k in (0, 2):
+                a = full[k + 1][full[k][g]:full[k][g + 1]]
+                b = part[k + 1][part[k][j]:part[k][j + 1]]
+                assert np.array_equal(a, b)
+    P = np.random.default_rng(0).normal(0, 0.1, 5057)
+    lf, fb = O.lists_learned(0.6, 0.4, 0.8, -3.0, 1.0, params=P)
+    lp, fbp = O.lists_learned(0.6, 0.4, 0.8, -3.0, 1.0, params=P, groups=sel)
+    for j, g in enumerate(sel):
+        for k in (0, 2):
+            assert np.array_equal(lf[k + 1][lf[k][g]:lf[k][g + 1]], lp[k + 1][lp[k][j]:lp[k][j + 1]])
+        assert fb[g] == fbp[j]
+    with pytest.raises(ValueError):
+        O.lists(0.5, groups=np.array([O.n_groups], np.int32))
+    with pytest.raises(ValueError):
+        O.lists_learned(0.6, 0.4, 0.8, -3.0, 1.0, params=P, groups=np.array([-1], np.int32))
