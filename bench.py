@@ -62,12 +62,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pos, m, w, gpu_acc, gpu_pot, plain=None, whole_limit=1 << 21):
+def cpu_baseline(pos, m, w, gpu_acc, gpu_pot, plain=None, whole_limit=1 << 21, sweep=None,
+                 lvt=None):
     """The oracle as it stands on the same workload: its own tree build, the
     same-tree walk and FP64 evaluation at theta = 0.5 of every group (the
     whole force call) up to `whole_limit` particles, above it of the groups
     that hold the 4096 sampled particles; the same sample on one core; and
-    the FP64 direct sum for the sampled particles (the tree-error reference)."""
+    the FP64 direct sum for the sampled particles (the tree-error reference).
+    With `sweep` (theta -> GPU outputs, compensated and plain), each angle's
+    outputs are judged on the sampled groups against the same-tree oracle and
+    on the sample against the FP64 direct sum; with `lvt` (the learned-vs-
+    theta comparison's sampled accelerations), both operating points' p99 is
+    judged against the FP64 direct sum."""
     import oracle
     cores = oracle.num_threads()
     n = pos.shape[0]
@@ -96,6 +102,17 @@ def cpu_baseline(pos, m, w, gpu_acc, gpu_pot, plain=None, whole_limit=1 << 21):
     O.forces(0.5, w["eps"], groups=sel)
     t_one = time.perf_counter() - t0
     oracle.set_threads(cores)
+    judged = {}
+    for th, r in (sweep or {}).items():
+        sa, sp = O.forces(th, w["eps"], groups=sel)
+        judged[th] = {"compensated_vs_same_tree_oracle": _errs((r["acc"], r["pot"]), sa, sp),
+                      "plain_vs_same_tree_oracle": _errs((r["plain_acc"], r["plain_pot"]), sa, sp),
+                      "vs_direct_fp64": oracle.err_summary(r["acc"][tg], ad),
+                      "same_tree_sample": f"the {len(sel)} groups ({n_sel} particles) holding "
+                                          f"the {len(tg)} sampled particles"}
+    lvt_fp64 = None
+    if lvt is not None:
+        lvt_fp64 = {k: oracle.err_summary(v, ad) for k, v in lvt.items()}
     what = (f"the whole force call ({O.n_groups} groups)" if whole else
             f"the {len(sel)} groups ({n_sel} particles) holding the {len(tg)} sampled particles")
     return {
@@ -114,6 +131,8 @@ def cpu_baseline(pos, m, w, gpu_acc, gpu_pot, plain=None, whole_limit=1 << 21):
                                     "particles": int(done.sum())},
         **({} if plain is None else {"gpu_plain_sum_vs_same_tree_oracle": _errs(plain, ar, pr)}),
         "gpu_vs_direct_fp64": oracle.err_summary(gpu_acc[tg], ad) | {"n": len(tg)},
+        **({"theta_sweep": judged} if judged else {}),
+        **({"learned_vs_theta_vs_direct_fp64": lvt_fp64} if lvt_fp64 else {}),
     }
 
 
@@ -183,7 +202,9 @@ def learned_vs_theta(T, w, steps, band=None, beta=30.0, target=1e-3, params=None
     """The learned acceptance criterion against the opening angle at equal
     p99 relative force error (against the GPU direct sum on the 4096-particle
     sample): theta* by bisection, then tau_pair (budget = beta * tau_pair) by
-    bisection in log tau, then both timed over `steps` force calls.  The
+    bisection in log tau, then both timed over `steps` force calls.  Returns
+    the summary and the sampled accelerations of both operating points (for
+    the FP64 judgement in the CPU-baseline leg).  The
     network decides in the band (theta* + a, theta* + b), band_rel = (a, b),
     or in the fixed `band` when one is given.
     The target is unreachable when the band's lower edge exceeds theta*
@@ -211,10 +232,15 @@ def learned_vs_theta(T, w, steps, band=None, beta=30.0, target=1e-3, params=None
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    def sampled(theta):
+        a, _ = T.forces(theta, eps, with_pot=False)
+        return a[sm].double().cpu().numpy()
+
     T.set_mac(None)
     th, e_th = L.bisect(p99, 0.3, 1.0, target, increasing=True)
     t_th = timed(th)
     c_th = T.last_counts()
+    acc_th = sampled(th)
     log(f"bench: theta* {th:.4f} p99 {e_th:.3e} {t_th * 1e3:.3f} ms")
     if band is None:
         band = (min(1.0, max(0.0, th + band_rel[0])), min(1.0, th + band_rel[1]))
@@ -229,6 +255,7 @@ def learned_vs_theta(T, w, steps, band=None, beta=30.0, target=1e-3, params=None
     t_l = timed(th)
     c_l = T.last_counts()
     st = T.mac_stats()
+    acc_l = sampled(th)
     T.set_mac(None)
     log(f"bench: learned tau {tau:.3e} p99 {e_l:.3e} {t_l * 1e3:.3f} ms")
     n = T.n
@@ -243,8 +270,53 @@ def learned_vs_theta(T, w, steps, band=None, beta=30.0, target=1e-3, params=None
                     "band_scored": st["band"], "groups_fell_back": st["fell_back"],
                     "groups": T.stats["n_groups"]},
         "speedup": t_th / t_l,
+        "flop_ratio": ((FLOP_PC * c_th["n_pc"] + FLOP_PP * c_th["n_pp"])
+                       / (FLOP_PC * c_l["n_pc"] + FLOP_PP * c_l["n_pp"])),
         "target_met": bool(e_l <= target),
-    }
+    }, {"theta_star": acc_th, "learned": acc_l}
+
+
+def theta_sweep(T, w, steps, thetas, path=None):
+    """Every opening angle of the workload's set on the same tree: `steps`
+    compensated force calls (host clock over the calls; the fused kernel's
+    HIP-event phase for the roofline fraction) and `steps` with plain FP32
+    accumulation.  Returns the per-angle summary and the host copies of the
+    outputs (for the oracle's judgement in the CPU-baseline leg)."""
+    import torch
+    eps, n = w["eps"], T.n
+    acc = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    pot = torch.empty(n, dtype=torch.float32, device="cuda")
+    summary, outputs = {}, {}
+
+    def run(theta, plain):
+        for _ in range(2):
+            T.forces(theta, eps, acc=acc, pot=pot, plain=plain, timed=True, path=path)
+        torch.cuda.synchronize()
+        ev = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            T.forces(theta, eps, acc=acc, pot=pot, plain=plain, timed=True, path=path)
+            ev.append(T.last_timings()["eval"])
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3, float(np.mean(ev))
+
+    for th in thetas:
+        ms, ev_ms = run(th, False)
+        c = T.last_counts()
+        a, p = acc.double().cpu().numpy(), pot.double().cpu().numpy()
+        ms_p, ev_p = run(th, True)
+        flops = FLOP_PP * c["n_pp"] + FLOP_PC * c["n_pc"]
+        summary[th] = {"ms_per_call": ms, "particles_per_s": n / (ms * 1e-3),
+                       "kernel_ms": ev_ms, "flops_per_launch": flops,
+                       "frac": flops / (ev_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                       "path_frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                       "interactions_per_particle": {"pc": c["n_pc"] / n, "pp": c["n_pp"] / n},
+                       "plain_ms_per_call": ms_p, "plain_kernel_ms": ev_p}
+        outputs[th] = {"acc": a, "pot": p, "plain_acc": acc.double().cpu().numpy(),
+                       "plain_pot": pot.double().cpu().numpy()}
+        log(f"bench: theta {th}: {ms:.3f} ms ({ev_ms:.3f} kernel, "
+            f"{summary[th]['frac'] * 100:.1f} % of peak), plain {ms_p:.3f} ms")
+    return summary, outputs
 
 
 def main():
@@ -276,6 +348,8 @@ def main():
                          "default: the shipped network)")
     ap.add_argument("--list-spread", action="store_true",
                     help="report per-group list lengths and per-work-item FLOPs (on for clumps4m)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the timing of the workload's other opening angles")
     ap.add_argument("--no-integration", action="store_true",
                     help="skip the leapfrog science-rate measurement")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -311,6 +385,9 @@ def main():
     log(f"bench: generating {args.workload} n={w['n']}")
     pos, m = W.make(args.workload)
     n = pos.shape[0]
+    # first use (library load, HIP context, allocator pools), then the timed build
+    og.Tree(pos, m, w["n_leaf"], 64)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     T = og.Tree(pos, m, w["n_leaf"], 64)
     torch.cuda.synchronize()
@@ -417,9 +494,14 @@ def main():
     if not args.no_integration and args.workload == "plummer1m":
         log("bench: leapfrog science rate ...")
         out["integration"] = integration_rate(n, theta, eps, args.steps)
+    sweep_out = None
+    if args.mac == "theta" and len(w.get("thetas", ())) > 1 and not args.no_sweep:
+        log(f"bench: opening angles {w['thetas']} ...")
+        out["theta_sweep"], sweep_out = theta_sweep(T, w, args.steps, w["thetas"], args.path)
+    lvt_acc = None
     if not args.no_learned:
         log("bench: learned criterion vs theta at p99 1e-3 ...")
-        out["learned_vs_theta"] = learned_vs_theta(
+        out["learned_vs_theta"], lvt_acc = learned_vs_theta(
             T, w, args.steps, band=tuple(args.band) if args.band else None, beta=args.beta,
             params=args.params, band_rel=tuple(args.band_rel))
     # FP32 plain accumulation (no compensation) on the same call, for comparison
@@ -439,7 +521,7 @@ def main():
         log("bench: cpu baseline (oracle) ...")
         a = acc.double().cpu().numpy()
         p = pot.double().cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(pos, m, w, a, p, plain)
+        out["cpu_baseline"] = cpu_baseline(pos, m, w, a, p, plain, sweep=sweep_out, lvt=lvt_acc)
         log("bench: cpu baseline done")
     print(json.dumps(out), flush=True)
 

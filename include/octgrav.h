@@ -176,6 +176,20 @@ int octgrav_lists(octgrav_tree* t, float theta, int64_t* c_off, int32_t* c_ids, 
 int octgrav_lists_ex(octgrav_tree* t, float theta, uint32_t flags, int64_t* c_off, int32_t* c_ids,
                      int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l);
 
+/*
+ * Interaction lists of selected groups (Sec. 2.2), for trees whose full lists
+ * would not fit in host memory: the walk covers every group as in
+ * octgrav_lists_ex (same flags, same lists on the device), and only the
+ * groups named in groups (host, n_sel int32 group indices in [0, n_groups),
+ * any order, repeats allowed; n_sel >= 0) are copied back, in that order:
+ * c_off and l_off hold n_sel+1 int64 offsets into c_ids / l_ids, and *n_c /
+ * *n_l the selection's total entries.  Two-call pattern as octgrav_lists.
+ * An index outside [0, n_groups) gives OCTGRAV_EINVAL before any launch.
+ */
+int octgrav_lists_select(octgrav_tree* t, float theta, uint32_t flags, const int32_t* groups,
+                         int64_t n_sel, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
+                         int32_t* l_ids, int64_t* n_c, int64_t* n_l);
+
 /* FP64 diagnostics of the last octgrav_forces call, reduced on the GPU:
  * mom = sum_i m_i a_i and *w = 1/2 sum_i m_i phi_i (0 if pot was NULL). */
 int octgrav_diagnostics(octgrav_tree* t, double mom[3], double* w);
@@ -293,6 +307,14 @@ int octgrav_mac_stats(octgrav_tree* t, int64_t out[2]);
  */
 int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells, float* scores,
                       int64_t cap, int64_t* n_out, int32_t* fell_back);
+
+/* As octgrav_mac_trace for the selected groups only (groups: host, n_sel
+ * int32 group indices in [0, n_groups), any order): off (n_sel+1) and
+ * fell_back (n_sel) follow the selection's order, cells / scores hold the
+ * selected groups' entries.  The learned walk itself covers every group. */
+int octgrav_mac_trace_select(octgrav_tree* t, float theta, const int32_t* groups, int64_t n_sel,
+                             int64_t* off, int32_t* cells, float* scores, int64_t cap,
+                             int64_t* n_out, int32_t* fell_back);
 
 /*
  * ---- Time integration (the step after the force call: the paper's science

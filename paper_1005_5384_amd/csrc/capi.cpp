@@ -701,6 +701,62 @@ int octgrav_forces(octgrav_tree* t, float theta, float eps, float* acc, float* p
   return octgrav_forces_ex(t, theta, eps, acc, pot, 0);
 }
 
+// Count walk, offsets and write walk of the path the flags select: the lists
+// of every group at theta end on the device (wb.c_off, wb.l_off, wb.c_ids,
+// wb.l_ids); *n_c, *n_l = entries.
+static int lists_to_device(octgrav_tree* t, float theta, uint32_t flags, int64_t* n_c,
+                           int64_t* n_l) {
+  t->counts_valid = false;
+  int64_t tot[8];
+  if (t->learned && (flags & (OCTGRAV_TWO_PASS | OCTGRAV_FUSED_BLOCK)))
+    return fail(OCTGRAV_EINVAL, "the learned criterion runs on the fused wave path only");
+  if (int rc = check_com(t, flags, theta)) return rc;
+  const bool com = flags & OCTGRAV_MAC_COM;
+  ComRecords cr(t, com, theta);
+  if (cr.rc) return cr.rc;
+  // Count walk and offsets give the sizes; the buffers are made to fit.
+  // (The learned criterion and the offset test count with the fused walk.)
+  t->wb.export_lists = 0;
+  const bool fused_count = t->learned || com;
+  if (fused_count ? launch_fused(t, Path::FusedWave, theta, 1.0f, false, false, nullptr, nullptr) != 0
+                  : launch_walk(t->dt, t->wb, theta, 0, t->stream) != 0)
+    return fail(OCTGRAV_EHIP, "count walk launch failed");
+  if (launch_scan(t->dt, t->wb, t->stream)) return fail(OCTGRAV_EHIP, "offsets launch failed");
+  if (int rc = t->read_tot(tot)) return rc;
+  if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+  if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
+  const Path path = fused_count ? Path::FusedWave : choose_path(flags, theta);
+  if (path == Path::TwoPass) {
+    if (launch_walk(t->dt, t->wb, theta, 1, t->stream)) return fail(OCTGRAV_EHIP, "write walk launch failed");
+  } else {
+    t->wb.export_lists = 1;
+    int rc = launch_fused(t, path, theta, 1.0f, false, false, nullptr, nullptr);
+    t->wb.export_lists = 0;
+    if (rc) return fail(OCTGRAV_EHIP, "walk (export) launch failed");
+  }
+  int64_t tot2[8];
+  if (int rc = t->read_tot(tot2)) return rc;
+  if (tot2[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+  if (tot2[0] != tot[0] || tot2[1] != tot[1])
+    return fail(OCTGRAV_ECAPACITY, "walk list sizes disagree with the count walk");
+  t->counts_valid = true;
+  *n_c = tot[0];
+  *n_l = tot[1];
+  return OCTGRAV_OK;
+}
+
+// A selection of group indices: n_sel >= 0 entries, each in [0, n_groups).
+static int check_selection(const octgrav_tree* t, const int32_t* groups, int64_t n_sel) {
+  if (n_sel < 0) return fail(OCTGRAV_EINVAL, "n_sel must be >= 0");
+  if (n_sel > 0 && !groups) return fail(OCTGRAV_EINVAL, "groups must be non-NULL when n_sel > 0");
+  const int64_t ng = t->h.n_groups();
+  for (int64_t k = 0; k < n_sel; ++k)
+    if (groups[k] < 0 || groups[k] >= ng)
+      return fail(OCTGRAV_EINVAL, "group index " + std::to_string(groups[k]) + " outside [0, " +
+                                      std::to_string(ng) + ")");
+  return OCTGRAV_OK;
+}
+
 int octgrav_lists_ex(octgrav_tree* t, float theta, uint32_t flags, int64_t* c_off, int32_t* c_ids,
                      int64_t* l_off, int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
   g_err.clear();
@@ -710,50 +766,62 @@ int octgrav_lists_ex(octgrav_tree* t, float theta, uint32_t flags, int64_t* c_of
   if (want && !(c_off && c_ids && l_off && l_ids))
     return fail(OCTGRAV_EINVAL, "give all four list arrays or none");
   try {
-    t->counts_valid = false;
-    int64_t tot[8];
-    if (t->learned && (flags & (OCTGRAV_TWO_PASS | OCTGRAV_FUSED_BLOCK)))
-      return fail(OCTGRAV_EINVAL, "the learned criterion runs on the fused wave path only");
-    if (int rc = check_com(t, flags, theta)) return rc;
-    const bool com = flags & OCTGRAV_MAC_COM;
-    ComRecords cr(t, com, theta);
-    if (cr.rc) return cr.rc;
-    // Count walk and offsets give the sizes; the buffers are made to fit.
-    // (The learned criterion and the offset test count with the fused walk.)
-    t->wb.export_lists = 0;
-    const bool fused_count = t->learned || com;
-    if (fused_count ? launch_fused(t, Path::FusedWave, theta, 1.0f, false, false, nullptr, nullptr) != 0
-                    : launch_walk(t->dt, t->wb, theta, 0, t->stream) != 0)
-      return fail(OCTGRAV_EHIP, "count walk launch failed");
-    if (launch_scan(t->dt, t->wb, t->stream)) return fail(OCTGRAV_EHIP, "offsets launch failed");
-    if (int rc = t->read_tot(tot)) return rc;
-    if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
-    if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
-    *n_c = tot[0];
-    *n_l = tot[1];
-    const Path path = fused_count ? Path::FusedWave : choose_path(flags, theta);
-    if (path == Path::TwoPass) {
-      if (launch_walk(t->dt, t->wb, theta, 1, t->stream)) return fail(OCTGRAV_EHIP, "write walk launch failed");
-    } else {
-      t->wb.export_lists = 1;
-      int rc = launch_fused(t, path, theta, 1.0f, false, false, nullptr, nullptr);
-      t->wb.export_lists = 0;
-      if (rc) return fail(OCTGRAV_EHIP, "walk (export) launch failed");
-    }
-    int64_t tot2[8];
-    if (int rc = t->read_tot(tot2)) return rc;
-    if (tot2[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
-    if (tot2[0] != tot[0] || tot2[1] != tot[1])
-      return fail(OCTGRAV_ECAPACITY, "walk list sizes disagree with the count walk");
-    t->counts_valid = true;
+    int64_t tc = 0, tl = 0;
+    if (int rc = lists_to_device(t, theta, flags, &tc, &tl)) return rc;
+    *n_c = tc;
+    *n_l = tl;
     if (want) {
       const int64_t ng = t->h.n_groups();
       if (hipMemcpy(c_off, t->wb.c_off, (ng + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
           hipMemcpy(l_off, t->wb.l_off, (ng + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-          (tot[0] && hipMemcpy(c_ids, t->wb.c_ids, tot[0] * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
-          (tot[1] && hipMemcpy(l_ids, t->wb.l_ids, tot[1] * 4, hipMemcpyDeviceToHost) != hipSuccess))
+          (tc && hipMemcpy(c_ids, t->wb.c_ids, tc * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+          (tl && hipMemcpy(l_ids, t->wb.l_ids, tl * 4, hipMemcpyDeviceToHost) != hipSuccess))
         return fail(OCTGRAV_EHIP, "list copy-back failed");
     }
+    return OCTGRAV_OK;
+  } catch (const std::exception& e) {
+    return fail(OCTGRAV_EHIP, e.what());
+  }
+}
+
+int octgrav_lists_select(octgrav_tree* t, float theta, uint32_t flags, const int32_t* groups,
+                         int64_t n_sel, int64_t* c_off, int32_t* c_ids, int64_t* l_off,
+                         int32_t* l_ids, int64_t* n_c, int64_t* n_l) {
+  g_err.clear();
+  if (int rc = check_theta(t, theta)) return rc;
+  if (!n_c || !n_l) return fail(OCTGRAV_EINVAL, "n_c and n_l must be non-NULL");
+  if (int rc = check_selection(t, groups, n_sel)) return rc;
+  const bool want = c_off || c_ids || l_off || l_ids;
+  if (want && !(c_off && c_ids && l_off && l_ids))
+    return fail(OCTGRAV_EINVAL, "give all four list arrays or none");
+  try {
+    int64_t tc = 0, tl = 0;
+    if (int rc = lists_to_device(t, theta, flags, &tc, &tl)) return rc;
+    const int64_t ng = t->h.n_groups();
+    std::vector<int64_t> co(ng + 1), lo(ng + 1);
+    if (hipMemcpy(co.data(), t->wb.c_off, (ng + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(lo.data(), t->wb.l_off, (ng + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(OCTGRAV_EHIP, "offset copy-back failed");
+    int64_t sc = 0, sl = 0;
+    for (int64_t k = 0; k < n_sel; ++k) {
+      const int32_t g = groups[k];
+      if (want) {
+        c_off[k] = sc;
+        l_off[k] = sl;
+        const int64_t kc = co[g + 1] - co[g], kl = lo[g + 1] - lo[g];
+        if ((kc && hipMemcpy(c_ids + sc, t->wb.c_ids + co[g], kc * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+            (kl && hipMemcpy(l_ids + sl, t->wb.l_ids + lo[g], kl * 4, hipMemcpyDeviceToHost) != hipSuccess))
+          return fail(OCTGRAV_EHIP, "list copy-back failed");
+      }
+      sc += co[g + 1] - co[g];
+      sl += lo[g + 1] - lo[g];
+    }
+    if (want) {
+      c_off[n_sel] = sc;
+      l_off[n_sel] = sl;
+    }
+    *n_c = sc;
+    *n_l = sl;
     return OCTGRAV_OK;
   } catch (const std::exception& e) {
     return fail(OCTGRAV_EHIP, e.what());
@@ -934,15 +1002,19 @@ int octgrav_mac_stats(octgrav_tree* t, int64_t out[2]) {
   return OCTGRAV_OK;
 }
 
-int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells, float* scores,
-                      int64_t cap, int64_t* n_out, int32_t* fell_back) {
-  g_err.clear();
+// Decision trace of the learned walks of the selected groups (sel == NULL:
+// every group, in order).  The walk itself always covers every group; the
+// selection only chooses what is copied back.
+static int mac_trace_impl(octgrav_tree* t, float theta, const int32_t* sel, int64_t n_sel,
+                          int64_t* off, int32_t* cells, float* scores, int64_t cap,
+                          int64_t* n_out, int32_t* fell_back) {
   if (int rc = check_theta(t, theta)) return rc;
   if (!t->learned) return fail(OCTGRAV_EINVAL, "the learned criterion is not set");
   if (!off || !n_out || !fell_back) return fail(OCTGRAV_EINVAL, "off, n_out and fell_back must be non-NULL");
   try {
     t->counts_valid = false;
     const int64_t ng = t->h.n_groups();
+    if (!sel) n_sel = ng;
     t->wb.export_lists = 0;
     if (launch_fused(t, Path::FusedWave, theta, 1.0f, false, false, nullptr, nullptr))
       return fail(OCTGRAV_EHIP, "walk launch failed");
@@ -951,25 +1023,29 @@ int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells
     if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
     std::vector<int32_t> w;
     if (int rc = read_band_counts(t, w)) return rc;
+    std::vector<int64_t> full(ng + 1);
+    full[0] = 0;
+    for (int64_t g = 0; g < ng; ++g) full[g + 1] = full[g] + (w[g] >> 1);
     off[0] = 0;
-    for (int64_t g = 0; g < ng; ++g) {
-      off[g + 1] = off[g] + (w[g] >> 1);
-      fell_back[g] = w[g] & 1;
+    for (int64_t k = 0; k < n_sel; ++k) {
+      const int64_t g = sel ? sel[k] : k;
+      off[k + 1] = off[k] + (w[g] >> 1);
+      fell_back[k] = w[g] & 1;
     }
-    *n_out = off[ng];
+    *n_out = off[n_sel];
     t->counts_valid = true;
     if (!cells || !scores) return OCTGRAV_OK;
-    if (cap < off[ng]) return fail(OCTGRAV_EINVAL, "trace arrays too small");
-    const int64_t nt = off[ng];
+    if (cap < off[n_sel]) return fail(OCTGRAV_EINVAL, "trace arrays too small");
+    const int64_t nt = full[ng];
     void *d_off = nullptr, *d_c = nullptr, *d_s = nullptr;
     int rc = OCTGRAV_OK;
-    if ((rc = t->dalloc(&d_off, (ng + 1) * 8)) || (rc = t->dalloc(&d_c, nt * 4)) ||
-        (rc = t->dalloc(&d_s, nt * 4))) {
+    if ((rc = t->dalloc(&d_off, (ng + 1) * 8)) || (rc = t->dalloc(&d_c, std::max<int64_t>(nt, 1) * 4)) ||
+        (rc = t->dalloc(&d_s, std::max<int64_t>(nt, 1) * 4))) {
       t->dfree(d_off);
       t->dfree(d_c);
       return rc;
     }
-    if (hipMemcpy(d_off, off, (ng + 1) * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(d_off, full.data(), (ng + 1) * 8, hipMemcpyHostToDevice) != hipSuccess) {
       t->dfree(d_off);
       t->dfree(d_c);
       t->dfree(d_s);
@@ -984,9 +1060,16 @@ int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells
     t->wb.tr_off = saved.tr_off;
     t->wb.tr_c = saved.tr_c;
     t->wb.tr_s = saved.tr_s;
-    if (!rc && (hipMemcpy(cells, d_c, nt * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(scores, d_s, nt * 4, hipMemcpyDeviceToHost) != hipSuccess))
+    if (!rc && !sel && nt &&
+        (hipMemcpy(cells, d_c, nt * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+         hipMemcpy(scores, d_s, nt * 4, hipMemcpyDeviceToHost) != hipSuccess))
       rc = fail(OCTGRAV_EHIP, "trace copy-back failed");
+    for (int64_t k = 0; !rc && sel && k < n_sel; ++k) {
+      const int64_t g = sel[k], len = full[g + 1] - full[g];
+      if (len && (hipMemcpy(cells + off[k], (int32_t*)d_c + full[g], len * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                  hipMemcpy(scores + off[k], (float*)d_s + full[g], len * 4, hipMemcpyDeviceToHost) != hipSuccess))
+        rc = fail(OCTGRAV_EHIP, "trace copy-back failed");
+    }
     t->dfree(d_off);
     t->dfree(d_c);
     t->dfree(d_s);
@@ -994,6 +1077,29 @@ int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells
   } catch (const std::exception& e) {
     return fail(OCTGRAV_EHIP, e.what());
   }
+}
+
+int octgrav_mac_trace(octgrav_tree* t, float theta, int64_t* off, int32_t* cells, float* scores,
+                      int64_t cap, int64_t* n_out, int32_t* fell_back) {
+  g_err.clear();
+  return mac_trace_impl(t, theta, nullptr, 0, off, cells, scores, cap, n_out, fell_back);
+}
+
+int octgrav_mac_trace_select(octgrav_tree* t, float theta, const int32_t* groups, int64_t n_sel,
+                             int64_t* off, int32_t* cells, float* scores, int64_t cap,
+                             int64_t* n_out, int32_t* fell_back) {
+  g_err.clear();
+  if (!t) return fail(OCTGRAV_EINVAL, "NULL handle");
+  if (int rc = check_selection(t, groups, n_sel)) return rc;
+  if (n_sel == 0) {  // an empty selection: nothing to walk for
+    if (int rc = check_theta(t, theta)) return rc;
+    if (!t->learned) return fail(OCTGRAV_EINVAL, "the learned criterion is not set");
+    if (!off || !n_out || !fell_back) return fail(OCTGRAV_EINVAL, "off, n_out and fell_back must be non-NULL");
+    off[0] = 0;
+    *n_out = 0;
+    return OCTGRAV_OK;
+  }
+  return mac_trace_impl(t, theta, groups, n_sel, off, cells, scores, cap, n_out, fell_back);
 }
 
 // ------------------------------------------------------------------ network

@@ -49,13 +49,14 @@ class TreeView(C.Structure):
 
 EXPORTED = ["octgrav_build_tree", "octgrav_build_tree_ex", "octgrav_forces", "octgrav_forces_ex",
             "octgrav_free", "octgrav_last_error", "octgrav_set_stream", "octgrav_tree_stats",
-            "octgrav_export_tree", "octgrav_lists", "octgrav_lists_ex", "octgrav_diagnostics",
+            "octgrav_export_tree", "octgrav_lists", "octgrav_lists_ex", "octgrav_lists_select",
+            "octgrav_diagnostics",
             "octgrav_last_counts", "octgrav_direct", "octgrav_mac_collect",
             "octgrav_last_timings", "octgrav_mlp_create", "octgrav_mlp_free",
             "octgrav_mlp_set_stream", "octgrav_mlp_set_params", "octgrav_mlp_get_params",
             "octgrav_mlp_get_moments", "octgrav_mlp_set_state",
             "octgrav_mlp_forward", "octgrav_mlp_loss_grad", "octgrav_mlp_adam", "octgrav_set_mac",
-            "octgrav_mac_stats", "octgrav_mac_trace", "octgrav_sim_create", "octgrav_sim_free",
+            "octgrav_mac_stats", "octgrav_mac_trace", "octgrav_mac_trace_select", "octgrav_sim_create", "octgrav_sim_free",
             "octgrav_sim_set_stream", "octgrav_sim_run", "octgrav_sim_energy", "octgrav_sim_state",
             "octgrav_sim_timings"]
 
@@ -90,6 +91,8 @@ def lib():
         L.octgrav_lists.argtypes = [vp, f32, vp, vp, vp, vp, C.POINTER(i64), C.POINTER(i64)]
         L.octgrav_lists_ex.argtypes = [vp, f32, C.c_uint32, vp, vp, vp, vp, C.POINTER(i64),
                                        C.POINTER(i64)]
+        L.octgrav_lists_select.argtypes = [vp, f32, C.c_uint32, vp, i64, vp, vp, vp, vp,
+                                           C.POINTER(i64), C.POINTER(i64)]
         L.octgrav_diagnostics.argtypes = [vp, vp, vp]
         L.octgrav_last_counts.argtypes = [vp, vp]
         L.octgrav_last_timings.argtypes = [vp, vp]
@@ -111,6 +114,8 @@ def lib():
         L.octgrav_set_mac.argtypes = [vp, vp, f32, f32, f32, f32]
         L.octgrav_mac_stats.argtypes = [vp, vp]
         L.octgrav_mac_trace.argtypes = [vp, f32, vp, vp, vp, i64, C.POINTER(i64), vp]
+        L.octgrav_mac_trace_select.argtypes = [vp, f32, vp, i64, vp, vp, vp, i64, C.POINTER(i64),
+                                               vp]
         L.octgrav_sim_create.restype = vp
         L.octgrav_sim_create.argtypes = [vp, vp, vp, i64, i32, i32]
         L.octgrav_sim_free.argtypes = [vp]
@@ -189,22 +194,28 @@ class Tree:
                                        None if pot is None else C.c_void_p(pot.data_ptr()), flags))
         return acc, pot
 
-    def lists(self, theta, two_pass=False, path=None, com=False):
+    def lists(self, theta, two_pass=False, path=None, com=False, groups=None):
         """(c_off, c_ids, l_off, l_ids) numpy CSR lists built by the GPU walk of
         the selected path (default: the force path's default for theta) and
-        opening test (com=True: the centre-of-mass offset test)."""
+        opening test (com=True: the centre-of-mass offset test); with `groups`
+        (group indices), only those groups' lists, in that order."""
         self._bind_stream()
         fl = (TWO_PASS if two_pass else 0) | PATHS[path] | (MAC_COM if com else 0)
         nc, nl = C.c_int64(), C.c_int64()
-        _check(lib().octgrav_lists_ex(self._h, float(theta), fl, None, None, None, None,
-                                      C.byref(nc), C.byref(nl)))
-        ng = self.stats["n_groups"]
+        if groups is None:
+            ng = self.stats["n_groups"]
+            fn = lambda *a: lib().octgrav_lists_ex(self._h, float(theta), fl, *a)
+        else:
+            sel = np.ascontiguousarray(groups, np.int32)
+            ng = sel.size
+            fn = lambda *a: lib().octgrav_lists_select(self._h, float(theta), fl, _ptr(sel),
+                                                       sel.size, *a)
+        _check(fn(None, None, None, None, C.byref(nc), C.byref(nl)))
         c_off = np.zeros(ng + 1, np.int64)
         l_off = np.zeros(ng + 1, np.int64)
         c_ids = np.zeros(max(1, nc.value), np.int32)
         l_ids = np.zeros(max(1, nl.value), np.int32)
-        _check(lib().octgrav_lists_ex(self._h, float(theta), fl, _ptr(c_off), _ptr(c_ids),
-                                      _ptr(l_off), _ptr(l_ids), C.byref(nc), C.byref(nl)))
+        _check(fn(_ptr(c_off), _ptr(c_ids), _ptr(l_off), _ptr(l_ids), C.byref(nc), C.byref(nl)))
         return c_off, c_ids[:nc.value], l_off, l_ids[:nl.value]
 
     def direct(self, eps, targets=None):
@@ -254,19 +265,25 @@ class Tree:
         _check(lib().octgrav_mac_stats(self._h, _ptr(out)))
         return dict(band=int(out[0]), fell_back=int(out[1]))
 
-    def mac_trace(self, theta):
-        """(off [ng+1], cells, scores, fell_back [ng]) of the learned walks."""
+    def mac_trace(self, theta, groups=None):
+        """(off [ng+1], cells, scores, fell_back [ng]) of the learned walks;
+        with `groups` (group indices), only those groups', in that order."""
         self._bind_stream()
-        ng = self.stats["n_groups"]
+        if groups is None:
+            ng = self.stats["n_groups"]
+            fn = lambda *a: lib().octgrav_mac_trace(self._h, float(theta), *a)
+        else:
+            sel = np.ascontiguousarray(groups, np.int32)
+            ng = sel.size
+            fn = lambda *a: lib().octgrav_mac_trace_select(self._h, float(theta), _ptr(sel),
+                                                           sel.size, *a)
         off = np.zeros(ng + 1, np.int64)
         fb = np.zeros(ng, np.int32)
         n = C.c_int64()
-        _check(lib().octgrav_mac_trace(self._h, float(theta), _ptr(off), None, None, 0,
-                                       C.byref(n), _ptr(fb)))
+        _check(fn(_ptr(off), None, None, 0, C.byref(n), _ptr(fb)))
         cells = np.zeros(max(1, n.value), np.int32)
         scores = np.zeros(max(1, n.value), np.float32)
-        _check(lib().octgrav_mac_trace(self._h, float(theta), _ptr(off), _ptr(cells),
-                                       _ptr(scores), cells.size, C.byref(n), _ptr(fb)))
+        _check(fn(_ptr(off), _ptr(cells), _ptr(scores), cells.size, C.byref(n), _ptr(fb)))
         return off, cells[:n.value], scores[:n.value], fb
 
     def export(self):

@@ -110,6 +110,29 @@ def test_lists_clumps_full():
     _gate(a[k], p[k], ar[k], pr[k], "clumps4m sampled")
 
 
+def test_lists_select_equals_slices(c1):
+    # The selected-group export (for trees whose full lists do not fit on the
+    # host) gives the full lists' slices, in the selection's order, repeats
+    # and an empty selection included, on every path and against the oracle's
+    # own selection.
+    pos, m, w, T, O = c1
+    ng = O.n_groups
+    sel = np.array([ng - 1, 0, 5, 5, ng // 2, 1], np.int32)
+    full = O.lists(0.5)
+    ref = O.lists(0.5, groups=sel)
+    c_off, c_ids, l_off, l_ids = full
+    for k, g in enumerate(sel):
+        assert np.array_equal(ref[1][ref[0][k]:ref[0][k + 1]], c_ids[c_off[g]:c_off[g + 1]])
+        assert np.array_equal(ref[3][ref[2][k]:ref[2][k + 1]], l_ids[l_off[g]:l_off[g + 1]])
+    for p_ in (None,) + PATHS:
+        _lists_equal(T.lists(0.5, path=p_, groups=sel), ref)
+    empty = T.lists(0.5, groups=np.zeros(0, np.int32))
+    assert empty[0].tolist() == [0] and empty[1].size == 0 and empty[3].size == 0
+    for bad in ([-1], [ng]):
+        with pytest.raises(og.OctgravError, match="outside"):
+            T.lists(0.5, groups=np.array(bad, np.int32))
+
+
 def test_lists_via_fallback_walk(c1):
     # A 64-entry LDS frontier overflows for almost every group, so the lists
     # come from the global-memory fallback walk; they must not change.
