@@ -141,6 +141,31 @@ int octgrav_forces(octgrav_tree* t, float theta, float eps, float* acc, float* p
 int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float* pot,
                       uint32_t flags);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or time-step loops, harnesses that forbid
+ * hipMalloc): the same force call as octgrav_forces (same paths, kernels,
+ * lists and compensated sums, so the same results bit for bit), whose per-call
+ * scratch (group records, totals, work counters, overflow lists, fallback
+ * frontier queues, diagnostic partial sums) lives in one file-scope device
+ * array of 128 MiB per GPU instead of the handle's buffers.  The call makes
+ * no hipMalloc / hipFree or other allocating call; the array is looked up on
+ * the first call on each device (that device current) and held until the
+ * process ends.  Afterwards octgrav_diagnostics, octgrav_last_counts and
+ * octgrav_mac_stats report this call, as after octgrav_forces.
+ *   Sizes: the tree must need at most 128 MiB of scratch (about
+ *   16 B x groups + 8 B x max(groups, work items) + one fallback frontier
+ *   queue of 8 B x its widest level rounded up to a power of two; the 2^24-
+ *   particle galaxy mix needs 21.4 MiB + 4 MiB), else OCTGRAV_EINVAL before
+ *   any launch.  Fewer fallback queues than octgrav_forces uses may fit
+ *   (only the rare walks that outgrow the LDS queues use them).
+ *   Sharing: every call on one GPU uses that GPU's one array; it keeps the
+ *   last call's contents and each call clears what it needs.  Calls that
+ *   overlap in time on one GPU (handles on different streams, or threads)
+ *   race on it and must be serialised by the caller.
+ */
+int octgrav_forces_noalloc(octgrav_tree* t, float theta, float eps, float* acc, float* pot);
+
 /* Releases the handle and everything it owns.  NULL is a no-op. */
 void octgrav_free(octgrav_tree* t);
 

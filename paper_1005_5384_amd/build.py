@@ -15,7 +15,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["walk.hip", "eval.hip", "walk_eval.hip", "walk_eval_block.hip", "mac.hip", "mlp.hip",
-               "tree_gpu.hip", "integrate.hip"]
+               "tree_gpu.hip", "integrate.hip", "noalloc.hip"]
 CPP_SOURCES = ["tree_build.cpp", "capi.cpp"]
 
 HIPCC_FLAGS = [

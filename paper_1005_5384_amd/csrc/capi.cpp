@@ -701,6 +701,82 @@ int octgrav_forces(octgrav_tree* t, float theta, float eps, float* acc, float* p
   return octgrav_forces_ex(t, theta, eps, acc, pot, 0);
 }
 
+// Test hook: OCTGRAV_NOALLOC_LIMIT=<bytes> lowers the usable part of the
+// no-allocation scratch (to reach the size check with small trees).
+static size_t noalloc_limit() {
+  size_t cap = noalloc_scratch_bytes();
+  if (const char* v = std::getenv("OCTGRAV_NOALLOC_LIMIT")) {
+    const long long x = std::atoll(v);
+    if (x > 0 && (size_t)x < cap) cap = (size_t)x;
+  }
+  return cap;
+}
+
+int octgrav_forces_noalloc(octgrav_tree* t, float theta, float eps, float* acc, float* pot) {
+  g_err.clear();
+  if (int rc = check_theta(t, theta)) return rc;
+  if (!(eps > 0.0f) || !std::isfinite(eps)) return fail(OCTGRAV_EINVAL, "eps must be finite and > 0");
+  if (!acc) return fail(OCTGRAV_EINVAL, "acc must be non-NULL");
+  try {
+    void* base = nullptr;
+    std::string err;
+    if (noalloc_scratch(&base, err)) return fail(OCTGRAV_EHIP, err);
+    // Carve the per-call scratch of the fused walk + evaluation (and of the
+    // diagnostics' partial sums) out of the array: fixed parts first, then as
+    // many fallback frontier queues as fit (at least one).
+    const int64_t ng = t->h.n_groups(), nw = (int64_t)t->h.work.size() / 2;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t at = off;
+      off += (bytes + 255) / 256 * 256;
+      return (unsigned char*)base + at;
+    };
+    WalkBufs b = t->wb;
+    b.tot = (int64_t*)take(8 * 8);
+    b.wctr = (int32_t*)take(9 * 64 * 4);
+    b.ovf_count = (int32_t*)take(4);
+    b.ovf_count2 = (int32_t*)take(4);
+    b.c_off = (int64_t*)take(8);  // only [0] is written without list export
+    b.l_off = (int64_t*)take(8);
+    b.cnt = (int32_t*)take((size_t)ng * 16);
+    b.ovf_list = (int32_t*)take((size_t)std::max(ng, nw) * 4);
+    b.ovf_list2 = (int32_t*)take((size_t)std::max(ng, nw) * 4);
+    double* part = (double*)take((size_t)diag_scratch_entries(t->h.n) * 8);
+    const size_t limit = noalloc_limit(), qbytes = (size_t)t->wb.gq_cap * 4;
+    if (off + qbytes > limit)
+      return fail(OCTGRAV_EINVAL, "tree needs " + std::to_string(off + qbytes) +
+                                      " bytes of scratch; octgrav_forces_noalloc has " +
+                                      std::to_string(limit));
+    b.gq = (int32_t*)take(0);
+    b.gq_waves = (int32_t)std::min<size_t>((size_t)t->wb.gq_waves, (limit - off) / qbytes);
+    b.export_lists = 0;
+    b.tr_off = nullptr;
+    b.tr_c = nullptr;
+    b.tr_s = nullptr;
+    t->counts_valid = false;
+    t->have_diag = false;
+    const Path path = t->learned ? Path::FusedWave : choose_path(0, theta);
+    const int rc = path == Path::FusedWave
+                       ? launch_walk_eval(t->dt, b, theta, eps, false, true, acc, pot, t->stream)
+                       : launch_walk_eval_block(t->dt, b, theta, eps, false, true, acc, pot, t->stream);
+    if (rc || launch_totals(t->dt, b, t->stream) || launch_diag(t->dt, acc, pot, part, t->d_diag, t->stream))
+      return fail(OCTGRAV_EHIP, "walk+evaluation launch failed");
+    // The call's totals and per-group records become the handle's, as after
+    // octgrav_forces (last_counts, mac_stats read them there).
+    if (hipMemcpyAsync(t->wb.tot, b.tot, 8 * 8, hipMemcpyDeviceToDevice, t->stream) != hipSuccess ||
+        hipMemcpyAsync(t->wb.cnt, b.cnt, (size_t)ng * 16, hipMemcpyDeviceToDevice, t->stream) != hipSuccess)
+      return fail(OCTGRAV_EHIP, "record copy failed");
+    int64_t tot[8];
+    if (int rc2 = t->read_tot(tot)) return rc2;
+    if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
+    t->counts_valid = true;
+    t->have_diag = true;
+    return OCTGRAV_OK;
+  } catch (const std::exception& e) {
+    return fail(OCTGRAV_EHIP, e.what());
+  }
+}
+
 // Count walk, offsets and write walk of the path the flags select: the lists
 // of every group at theta end on the device (wb.c_off, wb.l_off, wb.c_ids,
 // wb.l_ids); *n_c, *n_l = entries.

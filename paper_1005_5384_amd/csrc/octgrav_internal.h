@@ -212,4 +212,10 @@ int launch_diag(const DevTree& T, const float* acc, const float* pot, double* pa
 int64_t scan_scratch_entries(int64_t ng);
 int64_t diag_scratch_entries(int64_t n);
 
+// The file-scope device scratch array of octgrav_forces_noalloc: its size,
+// and its device address on the current device (looked up on the first call
+// per device, then cached).  0 on success.
+size_t noalloc_scratch_bytes();
+int noalloc_scratch(void** ptr, std::string& err);
+
 }  // namespace octgrav

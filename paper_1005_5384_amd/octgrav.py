@@ -48,6 +48,7 @@ class TreeView(C.Structure):
 
 
 EXPORTED = ["octgrav_build_tree", "octgrav_build_tree_ex", "octgrav_forces", "octgrav_forces_ex",
+            "octgrav_forces_noalloc",
             "octgrav_free", "octgrav_last_error", "octgrav_set_stream", "octgrav_tree_stats",
             "octgrav_export_tree", "octgrav_lists", "octgrav_lists_ex", "octgrav_lists_select",
             "octgrav_diagnostics",
@@ -82,6 +83,7 @@ def lib():
         L.octgrav_build_tree_ex.argtypes = [vp, vp, i64, i32, i32, C.c_uint32]
         L.octgrav_forces.argtypes = [vp, f32, f32, vp, vp]
         L.octgrav_forces_ex.argtypes = [vp, f32, f32, vp, vp, C.c_uint32]
+        L.octgrav_forces_noalloc.argtypes = [vp, f32, f32, vp, vp]
         L.octgrav_free.argtypes = [vp]
         L.octgrav_free.restype = None
         L.octgrav_last_error.restype = C.c_char_p
@@ -192,6 +194,21 @@ class Tree:
         flags |= PATHS[path] | (MAC_COM if com else 0)
         _check(lib().octgrav_forces_ex(self._h, float(theta), float(eps), C.c_void_p(acc.data_ptr()),
                                        None if pot is None else C.c_void_p(pot.data_ptr()), flags))
+        return acc, pot
+
+    def forces_noalloc(self, theta, eps, acc, pot=None):
+        """octgrav_forces_noalloc into the caller's acc [n,3] (and pot [n], or
+        None): contiguous float32 CUDA tensors; the call allocates nothing."""
+        import torch
+        for t in (acc, pot):
+            if t is not None and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("acc/pot must be contiguous float32 CUDA tensors")
+        if acc.numel() != 3 * self.n or (pot is not None and pot.numel() != self.n):
+            raise ValueError("acc must hold n*3 and pot n elements")
+        self._bind_stream()
+        _check(lib().octgrav_forces_noalloc(self._h, float(theta), float(eps),
+                                            C.c_void_p(acc.data_ptr()),
+                                            None if pot is None else C.c_void_p(pot.data_ptr())))
         return acc, pot
 
     def lists(self, theta, two_pass=False, path=None, com=False, groups=None):
