@@ -20,7 +20,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = ("particles/s and % FP32 VALU peak at N=2^20, learned vs θ-MAC at p99 err 1e-3")
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (spec sheet)
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (spec sheet; reached only with packed FP32)
+# Non-packed FP32 (the instructions the force kernels are built with): one
+# wave64 FMA per SIMD per 4 cycles, 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz.
+PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 FLOP_PP, FLOP_PC = 38, 70  # the paper's per-interaction convention (Sec. 3.3)
 
 
@@ -56,6 +59,17 @@ def recorded(path, key):
 def recorded_traffic():
     """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy)."""
     return recorded(TRAFFIC_PROFILE, "traffic_bytes")
+
+
+def valu_rate():
+    """Measured issue rate of non-packed VALU instructions (the library's
+    measurement program, run as a child process)."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1005_5384_amd", "valu_rate")
+    if not os.path.exists(exe):
+        return None
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    return json.loads(r.stdout) if r.returncode == 0 else None
 
 
 def log(*a):
@@ -309,6 +323,7 @@ def theta_sweep(T, w, steps, thetas, path=None):
         summary[th] = {"ms_per_call": ms, "particles_per_s": n / (ms * 1e-3),
                        "kernel_ms": ev_ms, "flops_per_launch": flops,
                        "frac": flops / (ev_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                       "frac_nonpacked": flops / (ev_ms * 1e-3) / 1e12 / PEAK_FP32_NONPACKED_TFLOPS,
                        "path_frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
                        "interactions_per_particle": {"pc": c["n_pc"] / n, "pp": c["n_pp"] / n},
                        "plain_ms_per_call": ms_p, "plain_kernel_ms": ev_p}
@@ -348,6 +363,8 @@ def main():
                          "default: the shipped network)")
     ap.add_argument("--list-spread", action="store_true",
                     help="report per-group list lengths and per-work-item FLOPs (on for clumps4m)")
+    ap.add_argument("--no-valu-rate", action="store_true",
+                    help="skip the measurement of the non-packed VALU instruction rates")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the timing of the workload's other opening angles")
     ap.add_argument("--no-integration", action="store_true",
@@ -459,7 +476,9 @@ def main():
                      "traffic": (recorded_traffic() if (args.workload == "plummer1m" and theta == 0.5
                                                         and args.path is None and args.mac == "theta")
                                  else None),
-                     "flops_per_launch": flops, "flop_convention": "38 per p-p, 70 per p-c"},
+                     "flops_per_launch": flops, "flop_convention": "38 per p-p, 70 per p-c",
+                     "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+                     "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS},
         "hw_fp32": None,
         "path_frac_peak": path_tflops / PEAK_FP32_TFLOPS,
         "path_tflops": path_tflops,
@@ -482,6 +501,7 @@ def main():
         # counts more per interaction than the instructions execute.
         out["hw_fp32"] = {"flops_per_launch": hw, "tflops": hw / eval_s / 1e12,
                           "frac": hw / eval_s / 1e12 / PEAK_FP32_TFLOPS,
+                          "frac_nonpacked": hw / eval_s / 1e12 / PEAK_FP32_NONPACKED_TFLOPS,
                           "counters": "SQ_INSTS_VALU_FLOPS_FP32 + SQ_INSTS_VALU_FLOPS_FP32_TRANS"}
     if args.mac == "learned":
         out["config"].update({"tau_pair": args.tau, "theta_lo": band[0],
@@ -494,6 +514,9 @@ def main():
     if not args.no_integration and args.workload == "plummer1m":
         log("bench: leapfrog science rate ...")
         out["integration"] = integration_rate(n, theta, eps, args.steps)
+    if not args.no_valu_rate:
+        log("bench: VALU issue-rate probe ...")
+        out["valu_rate"] = valu_rate()
     sweep_out = None
     if args.mac == "theta" and len(w.get("thetas", ())) > 1 and not args.no_sweep:
         log(f"bench: opening angles {w['thetas']} ...")

@@ -11,6 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libocgrav.so")
+# measurement program: issue rate of non-packed FP32 / INT32 VALU instructions
+VALU_RATE = os.path.join(HERE, "valu_rate")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
@@ -58,6 +60,9 @@ def build(verbose: bool = False, extra_hip_flags=()) -> str:
     _run([f"{ROCM}/bin/hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
           *[o for _, o in jobs], "-lgomp", "-Wl,--no-undefined", f"-Wl,-rpath,{ROCM}/lib"], verbose)
     os.replace(tmp, LIB)
+    _run([f"{ROCM}/bin/hipcc", *HIPCC_FLAGS, "-o", VALU_RATE + ".tmp",
+          os.path.join(CSRC, "valu_rate.hip")], verbose)
+    os.replace(VALU_RATE + ".tmp", VALU_RATE)
     return LIB
 
 
