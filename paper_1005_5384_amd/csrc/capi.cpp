@@ -81,8 +81,8 @@ struct octgrav_mlp {
     allocs.push_back(*p);
     return OCTGRAV_OK;
   }
-  // Training scratch for batches of up to b samples: 3 b + 4 x 64 b floats
-  // and the partial gradient sums.
+  // Training scratch for batches of up to b samples (activations, gradients
+  // and the partial gradient sums of launch_mlp_loss_grad).
   int reserve(int64_t b) {
     if (b <= scratch_b) return OCTGRAV_OK;
     if (scratch) {
@@ -91,7 +91,7 @@ struct octgrav_mlp {
       scratch = nullptr;
       scratch_b = 0;
     }
-    if (int rc = alloc(&scratch, ((size_t)(3 + 4 * 64) * b + mlp_grad_scratch_floats()) * 4))
+    if (int rc = alloc(&scratch, (size_t)mlp_train_scratch_floats(b) * 4))
       return rc;
     scratch_b = b;
     return OCTGRAV_OK;
@@ -1275,11 +1275,8 @@ int octgrav_mlp_loss_grad(octgrav_mlp* m, const float* x, const float* target, i
   if (b < 1 || !x || !target) return fail(OCTGRAV_EINVAL, "bad batch arguments");
   if (!(tau > 0.0f && tau < 1.0f)) return fail(OCTGRAV_EINVAL, "tau must be in (0, 1)");
   if (int rc = m->reserve(b)) return rc;
-  float* s = (float*)m->scratch;
-  float *y = s, *dys = y + b, *losss = dys + b, *a1 = losss + b, *a2 = a1 + 64 * b,
-        *dh1 = a2 + 64 * b, *dh2 = dh1 + 64 * b, *part = dh2 + 64 * b;
-  if (launch_mlp_loss_grad(m->pk, x, target, b, tau, y, a1, a2, dh1, dh2, dys, losss, part,
-                           (float*)m->grad, (double*)m->d_loss, m->stream) ||
+  if (launch_mlp_loss_grad(m->pk, x, target, b, tau, (float*)m->scratch, (float*)m->grad,
+                           (double*)m->d_loss, m->stream) ||
       hipMemcpyAsync(loss, m->d_loss, 8, hipMemcpyDeviceToHost, m->stream) != hipSuccess ||
       (grad && hipMemcpyAsync(grad, m->grad, kMlpParams * 4, hipMemcpyDeviceToHost, m->stream) !=
                    hipSuccess) ||

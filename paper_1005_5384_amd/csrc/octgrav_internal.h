@@ -152,9 +152,8 @@ int launch_mlp_pack(const float* P, void* pk, void* stream);
 int launch_mlp_forward(const void* pk, const float* x, int64_t B, float* y, float* a1s, float* a2s,
                        void* stream);
 int launch_mlp_loss_grad(const void* pk, const float* x, const float* tgt, int64_t B, float tau,
-                         float* y, float* a1s, float* a2s, float* dh1s, float* dh2s, float* dys,
-                         float* losss, float* part, float* grad, double* loss, void* stream);
-int64_t mlp_grad_scratch_floats();  // partial gradient sums of launch_mlp_loss_grad
+                         float* scratch, float* grad, double* loss, void* stream);
+int64_t mlp_train_scratch_floats(int64_t B);  // scratch of launch_mlp_loss_grad
 int launch_mlp_adam(float* P, float* m, float* v, const float* g, float lr, float b1, float b2,
                     float eps, float c1, float c2, void* stream);
 // Device tree build (same result as build_host_tree, computed on the GPU).

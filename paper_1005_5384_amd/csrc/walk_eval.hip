@@ -385,9 +385,14 @@ __device__ __forceinline__ int take_work(int32_t* ctr, int lane) {
 // cost), and a wave whose XCD's range is exhausted helps the other XCDs;
 // with FROM_LIST the items are the *src_n entries of src (the overflows of
 // an earlier tier), handed out through one counter.  Items whose frontier
-// outgrows this kernel's LDS queue are appended to (ovl, ovn).
+// outgrows this kernel's LDS queue are appended to (ovl, ovn).  Blocks of 16
+// waves (the learned criterion: one network copy per CU) are held to 128
+// VGPRs so that four waves per SIMD fit; the few registers this spills are
+// outside the loops (the same lists took 13 % longer than in the opening-
+// angle kernel at three waves per SIMD, 6 % at four).
 template <bool PLAIN, int QCAP, bool LEARNED, int NW, bool FROM_LIST>
-__global__ __launch_bounds__(NW * kLanes) void walk_eval_persistent_kernel(
+__global__ __launch_bounds__(NW * kLanes) __attribute__((amdgpu_waves_per_eu(NW == 16 ? 4 : 1)))
+void walk_eval_persistent_kernel(
     DevTree T, WalkBufs B, float th2, float eps2, float* acc, float* pot, int do_eval,
     const int32_t* src, const int32_t* src_n, int32_t* ovl, int32_t* ovn) {
   __shared__ WShared<QCAP> shw[NW];
@@ -499,8 +504,9 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
       walk_eval_persistent_kernel<P, 4096, L, 1, false><<<8 * 224, kLanes, 0, s>>>(
           T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list2, B.ovf_count2);
     } else {
-      if constexpr (L)  // 3 blocks of 4 waves per CU (4 x 9 KB frontiers + 12 KB network)
-        walk_eval_persistent_kernel<P, 1024, L, 4, false><<<8 * 96, 4 * kLanes, 0, s>>>(
+      if constexpr (L)  // one block of 16 waves per CU (16 x 9 KB frontiers + 12 KB network,
+                        // 159.6 KB of LDS), four per SIMD at <= 128 VGPRs
+        walk_eval_persistent_kernel<P, 1024, L, 16, false><<<8 * 32, 16 * kLanes, 0, s>>>(
             T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list, B.ovf_count);
       else  // 4 blocks of 4 waves per CU
         walk_eval_persistent_kernel<P, 1024, L, 4, false><<<8 * 128, 4 * kLanes, 0, s>>>(
