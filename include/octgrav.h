@@ -54,7 +54,7 @@ extern "C" {
  * OCTGRAV_TWO_PASS    count walk, offsets, write walk and evaluation kernels (the paper's
  *                     structure), pipelined over batches of groups on two streams;
  * OCTGRAV_FUSED_BLOCK one 256-thread block per group walks and evaluates (lists stay in LDS);
- * OCTGRAV_FUSED_WAVE  one 64-lane wave per group walks and evaluates. */
+ * OCTGRAV_FUSED_WAVE  one 64-lane wave per group walks and evaluates (the default). */
 #define OCTGRAV_TWO_PASS 4u
 #define OCTGRAV_FUSED_BLOCK 8u
 #define OCTGRAV_FUSED_WAVE 16u
@@ -112,7 +112,8 @@ typedef struct {
  * Groups are the maximal cells with at most 64 particles (Sec. 2.1).  The
  * inputs are copied; the caller may free them when the call returns.  The
  * handle owns all internal host and device memory until octgrav_free.
- * Returns NULL on failure.
+ * Returns NULL on failure, also for a tree of 2^29 cells or more (the walks'
+ * frontier entries hold cell ids in 29 bits).
  */
 octgrav_tree* octgrav_build_tree(const float* pos, const float* mass, int64_t n, int32_t n_leaf);
 
@@ -132,8 +133,8 @@ octgrav_tree* octgrav_build_tree_ex(const float* pos, const float* mass, int64_t
  *   acc    device, n x 3 FP32, caller's order (written)
  *   pot    device, n FP32, caller's order (written), or NULL
  * Runs on the handle's stream and returns once the results are complete on it.
- * All paths evaluate the same lists; the default picks the fastest measured
- * one for theta (the fused block walk below 0.40, the fused wave walks above).
+ * All paths evaluate the same lists; the default is the fastest measured one
+ * at every theta, the fused wave walk.
  */
 int octgrav_forces(octgrav_tree* t, float theta, float eps, float* acc, float* pot);
 
@@ -155,8 +156,8 @@ int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float
  * octgrav_mac_stats report this call, as after octgrav_forces.
  *   Sizes: the tree must need at most 128 MiB of scratch (about
  *   16 B x groups + 8 B x max(groups, work items) + one fallback frontier
- *   queue of 8 B x its widest level rounded up to a power of two; the 2^24-
- *   particle galaxy mix needs 21.4 MiB + 4 MiB), else OCTGRAV_EINVAL before
+ *   queue of 8 B x (2 x its widest level + 64) rounded up to a power of two;
+ *   the 2^24-particle galaxy mix needs 21.4 MiB + 8 MiB), else OCTGRAV_EINVAL before
  *   any launch.  Fewer fallback queues than octgrav_forces uses may fit
  *   (only the rare walks that outgrow the LDS queues use them).
  *   Sharing: every call on one GPU uses that GPU's one array; it keeps the

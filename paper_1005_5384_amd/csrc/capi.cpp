@@ -290,6 +290,9 @@ struct octgrav_tree : DevAlloc {
   // the tree arrays are on the device, from either build).
   int alloc_walk_buffers() {
     const int64_t n = h.n, ng = h.n_groups(), nw = (int64_t)h.work.size() / 2;
+    if (dt.nc >= (int64_t(1) << 29))  // the walks' queue entries hold cell id << 3
+      return fail(OCTGRAV_EINVAL, "tree has " + std::to_string(dt.nc) +
+                                      " cells; the walks address at most 2^29 - 1");
     int rc;
     void* p;
     if ((rc = dalloc(&p, (size_t)ng * 16))) return rc;
@@ -313,14 +316,15 @@ struct octgrav_tree : DevAlloc {
     if ((rc = dalloc(&p, 9 * 64 * 4))) return rc;
     wb.wctr = (int32_t*)p;
     // Fallback frontier queues: a breadth-first FIFO never holds more than
-    // two consecutive levels, hence at most twice the widest level.
+    // two consecutive levels, hence at most twice the widest level; entries
+    // of two words (the fused wave walk's child ranges).
     int64_t cap = 64;
     while (cap < 2 * h.max_level_cells + 64) cap <<= 1;
     wb.gq_cap = cap;
     wb.gq_waves = fallback_waves();
     // At most 4 GiB of queues.
-    while (wb.gq_waves > 64 && (int64_t)wb.gq_waves * cap * 4 > (int64_t(1) << 32)) wb.gq_waves >>= 1;
-    if ((rc = dalloc(&p, (size_t)wb.gq_waves * cap * 4))) return rc;
+    while (wb.gq_waves > 64 && (int64_t)wb.gq_waves * cap * 8 > (int64_t(1) << 32)) wb.gq_waves >>= 1;
+    if ((rc = dalloc(&p, (size_t)wb.gq_waves * cap * 8))) return rc;
     wb.gq = (int32_t*)p;
     wb.lds_qcap = lds_queue_entries();
     wb.export_lists = 0;
@@ -547,18 +551,17 @@ int octgrav_export_tree(const octgrav_tree* t, const octgrav_tree_view* v) {
 
 enum class Path { TwoPass, FusedBlock, FusedWave };
 
-// Path of a call: an explicit flag, else the fastest measured for theta
-// (2^20 Plummer, 4M clumps and 2^20 Milky-Way-like sets; ms at theta 0.38 /
-// 0.40 / 0.42, fused block: Plummer 6.3 / 5.5 / 5.1, clumps 24.7 / 21.7 /
-// 19.9, Milky Way 8.8 / 7.4 / 7.0; fused wave: 8.2 / 5.4 / 4.6, 25.0 / 17.4 /
-// 15.7, 9.5 / 6.1 / 5.4; the two-pass path trails both).  At small angles the
-// wave variant's 4096-entry LDS queues allow only a few walks per CU, where
-// the block variant shares one queue among four waves.
-static Path choose_path(uint32_t flags, float theta) {
+// Path of a call: an explicit flag, else the fused wave walk, the fastest
+// measured at every angle (ms, fused wave / fused block, at theta 0.3, 0.35,
+// 0.4, 0.5: 2^20 Plummer 8.95 / 11.0, 6.19 / 7.60, 4.30 / 5.46, 2.59 / 3.19;
+// 4M clumps 34.5 / 43.4, 23.5 / 30.0, 16.8 / 21.6, 10.2 / 12.6; the two-pass
+// path trails both).  The wave walk's queue entries of up to eight children
+// keep its 512-entry LDS frontiers from overflowing down to theta 0.3, so it
+// runs 16 walks per CU where the block walk runs four.
+static Path choose_path(uint32_t flags) {
   if (flags & OCTGRAV_TWO_PASS) return Path::TwoPass;
   if (flags & OCTGRAV_FUSED_BLOCK) return Path::FusedBlock;
-  if (flags & OCTGRAV_FUSED_WAVE) return Path::FusedWave;
-  return theta < 0.40f ? Path::FusedBlock : Path::FusedWave;  // measured crossover
+  return Path::FusedWave;
 }
 
 static int launch_fused(const octgrav_tree* t, Path p, float theta, float eps, bool plain,
@@ -631,7 +634,7 @@ int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float
       return fail(OCTGRAV_EINVAL, "the learned criterion runs on the fused wave path only");
     if (int rc = check_com(t, flags, theta)) return rc;
     const bool com = flags & OCTGRAV_MAC_COM;
-    const Path path = (t->learned || com) ? Path::FusedWave : choose_path(flags, theta);
+    const Path path = (t->learned || com) ? Path::FusedWave : choose_path(flags);
     ComRecords cr(t, com, theta);
     if (cr.rc) return cr.rc;
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -657,14 +660,20 @@ int octgrav_forces_ex(octgrav_tree* t, float theta, float eps, float* acc, float
         return fail(OCTGRAV_EHIP, "diagnostics launch failed");
       if (timed) hipEventRecord(t->ev[5], t->stream);
       if (int rc = t->read_tot(tot)) return rc;
-      if (debug_trace())
+      if (debug_trace()) {
+        int32_t ovf[2] = {0, 0};  // work items redone by the second / last walk tier
+        if (path != Path::TwoPass) {
+          hipMemcpy(&ovf[0], t->wb.ovf_count, 4, hipMemcpyDeviceToHost);
+          hipMemcpy(&ovf[1], t->wb.ovf_count2, 4, hipMemcpyDeviceToHost);
+        }
         std::fprintf(stderr,
                      "octgrav: attempt %d path %d slots %lld/%lld cap %lld/%lld tot %lld %lld %lld "
-                     "%lld %lld %lld %lld %lld\n",
+                     "%lld %lld %lld %lld %lld overflow %d %d\n",
                      attempt, (int)path, (long long)t->slot_c, (long long)t->slot_l,
                      (long long)t->wb.cap_c, (long long)t->wb.cap_l, (long long)tot[0],
                      (long long)tot[1], (long long)tot[2], (long long)tot[3], (long long)tot[4],
-                     (long long)tot[5], (long long)tot[6], (long long)tot[7]);
+                     (long long)tot[5], (long long)tot[6], (long long)tot[7], ovf[0], ovf[1]);
+      }
       if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
       if (path != Path::TwoPass) break;
       const bool slotted = t->slot_c > 0 && attempt == 0;
@@ -742,7 +751,7 @@ int octgrav_forces_noalloc(octgrav_tree* t, float theta, float eps, float* acc, 
     b.ovf_list = (int32_t*)take((size_t)std::max(ng, nw) * 4);
     b.ovf_list2 = (int32_t*)take((size_t)std::max(ng, nw) * 4);
     double* part = (double*)take((size_t)diag_scratch_entries(t->h.n) * 8);
-    const size_t limit = noalloc_limit(), qbytes = (size_t)t->wb.gq_cap * 4;
+    const size_t limit = noalloc_limit(), qbytes = (size_t)t->wb.gq_cap * 8;
     if (off + qbytes > limit)
       return fail(OCTGRAV_EINVAL, "tree needs " + std::to_string(off + qbytes) +
                                       " bytes of scratch; octgrav_forces_noalloc has " +
@@ -755,7 +764,7 @@ int octgrav_forces_noalloc(octgrav_tree* t, float theta, float eps, float* acc, 
     b.tr_s = nullptr;
     t->counts_valid = false;
     t->have_diag = false;
-    const Path path = t->learned ? Path::FusedWave : choose_path(0, theta);
+    const Path path = t->learned ? Path::FusedWave : choose_path(0);
     const int rc = path == Path::FusedWave
                        ? launch_walk_eval(t->dt, b, theta, eps, false, true, acc, pot, t->stream)
                        : launch_walk_eval_block(t->dt, b, theta, eps, false, true, acc, pot, t->stream);
@@ -801,7 +810,7 @@ static int lists_to_device(octgrav_tree* t, float theta, uint32_t flags, int64_t
   if (int rc = t->read_tot(tot)) return rc;
   if (tot[5]) return fail(OCTGRAV_ECAPACITY, "fallback walk frontier overflow");
   if (int rc = t->reserve_lists(tot[0], tot[1])) return rc;
-  const Path path = fused_count ? Path::FusedWave : choose_path(flags, theta);
+  const Path path = fused_count ? Path::FusedWave : choose_path(flags);
   if (path == Path::TwoPass) {
     if (launch_walk(t->dt, t->wb, theta, 1, t->stream)) return fail(OCTGRAV_EHIP, "write walk launch failed");
   } else {

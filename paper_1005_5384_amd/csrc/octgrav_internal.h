@@ -91,10 +91,12 @@ struct WalkBufs {
   int32_t* ovf_count2; // [1]
   int32_t* wctr;       // [9 x 64]: work counters (stride 64) of persistent kernels:
                        // 8 per-XCD ranges, 1 overflow list
-  int32_t* gq;         // global frontier queues for the fallback walk
+  int32_t* gq;         // global frontier queues for the fallback walk: 2 * gq_cap words each
   int64_t gq_cap;      // entries per queue (power of two)
   int32_t gq_waves;    // queues (waves) of the fallback walk
-  int32_t lds_qcap;    // cap on the LDS frontier entries used (power of two; test hook)
+  int32_t lds_qcap;    // cap on the LDS frontier in candidates (power of two >= 64; test
+                       // hook); the fused wave walk's entries of up to eight children use
+                       // lds_qcap / 8 of them
   int32_t export_lists;  // fused walk: also write the lists at c_off / l_off
   // Slotted lists (walk mode 2, > 0): group g's lists start at g * slot_c /
   // g * slot_l and their lengths are cnt[g].x / .y; 0 = CSR offsets.

@@ -16,14 +16,18 @@
 // order, ballot compaction in lane order), so the cell and leaf lists are
 // identical; an export mode writes them at offsets from the count walk for
 // the parity tests.  Each candidate costs one 32-byte gather (boundary +
-// topology).  Evaluation: the wave splits into S = floor(64 / n) slices of n
+// topology).  The frontier FIFO holds one entry per opened cell (its
+// children are consecutive cells): a step takes the next 64 children of the
+// queued entries, finding each lane's entry with one mark per entry in LDS
+// and a ballot, so an opened cell costs one store instead of one per child,
+// and a queue entry stands for up to eight candidates.  Evaluation: the wave splits into S = floor(64 / n) slices of n
 // lanes; every slice holds all n targets and takes every S-th source of a
 // tile; plain FP32 per tile is folded into Neumaier pairs; slices are
 // combined in slice order.
 //
 // A work item whose frontier outgrows its LDS queue aborts before writing any
-// result and is redone by the next tier: 1024-entry LDS queues, then
-// 4096-entry LDS queues, then queues in global memory sized so that they
+// result and is redone by the next tier: 512-entry LDS queues, then
+// 2048-entry LDS queues, then queues in global memory sized so that they
 // cannot overflow.
 //
 // Learned acceptance criterion (LEARNED): candidates the test at theta_lo
@@ -53,9 +57,11 @@ constexpr int kLanes = 64;
 constexpr int kTileW = 64;   // sources per tile
 constexpr int kRingW = 128;  // pending cells / leaves (two tiles)
 
+// Frontier entry: x = first child << 3 | (children - 1) (cell ids < 2^29),
+// y = position of the first child in the item's candidate sequence.
 template <int QCAP>
 struct WShared {
-  int q[QCAP];
+  int2 q[QCAP];
   int cring[kRingW];
   int2 lring[kRingW];  // (first particle, n particles) of opened leaves
   float4 tile[3 * kTileW];
@@ -70,6 +76,13 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// LDS frontier queue of one wave.
+struct LQueue {
+  int2* p;
+  __device__ int2 get(uint32_t i) const { return p[i]; }
+  __device__ void put(uint32_t i, int x, int y) const { p[i] = make_int2(x, y); }
+};
 
 template <bool PLAIN, typename SH>
 struct WItem {
@@ -189,7 +202,10 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
   const int64_t xcb = exp ? B.c_off[g] : 0, xce = exp ? B.c_off[g + 1] : 0;
   const int64_t xlb = exp ? B.l_off[g] : 0, xle = exp ? B.l_off[g + 1] : 0;
 
-  uint32_t head = 0, tail = 0, chead = 0, ctail = 0, lhead = 0, ltail = 0;
+  // Frontier: entries [rhead, rtail) of q; candidates [vhead, vtail) of the
+  // item's breadth-first sequence (the entry at rhead may be partly taken).
+  uint32_t rhead = 0, rtail = 0, vhead = 0, vtail = 0;
+  uint32_t chead = 0, ctail = 0, lhead = 0, ltail = 0;
   const int4 root = reinterpret_cast<const int4*>(rec)[1];
   if (root.y == 0) {  // the root is a leaf: its particles are the whole list
     if (lane == 0) {
@@ -198,28 +214,47 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
     }
     ltail = 1;
   } else {
-    if (lane < root.y) q[lane] = root.x + lane;
-    tail = (uint32_t)root.y;
+    if (lane == 0) q.put(0, (root.x << 3) | (root.y - 1), 0);
+    rtail = 1;
+    vtail = (uint32_t)root.y;
   }
+  // Each step marks, in sh.lfirst, the lane at which each taken entry's
+  // children begin, with a value no earlier step of this item used
+  // (-1 - vhead) and that no particle index equals.
+  sh.lfirst[lane] = 0;
   if (gmem_q) __threadfence_block();  // queue stores complete before other lanes read
   wave_lds_sync();
 
-  while (head < tail) {
-    const uint32_t navail = min((uint32_t)kLanes, tail - head);
+  while (vhead < vtail) {
+    const uint32_t nent = min((uint32_t)kLanes, rtail - rhead);
+    const uint32_t navail = min((uint32_t)kLanes, vtail - vhead);
+    const bool inq = (uint32_t)lane < nent;
+    int2 e = make_int2(0, 0);
+    if (inq) e = q.get((rhead + lane) & qmask);
+    // First lane of this entry's children in the step (<= 0 for the partly
+    // taken head entry) and one past its last.
+    const int s0 = (int)((uint32_t)e.y - vhead);
+    const int s1 = s0 + (int)((uint32_t)e.x & 7u) + 1;
+    const bool inwin = inq && s0 < kLanes;
+    const int stamp = -1 - (int)vhead;
+    if (inwin) sh.lfirst[max(s0, 0)] = stamp;
+    wave_lds_sync();
+    const bool mark = sh.lfirst[lane] == stamp;
+    const uint64_t mM = __ballot(mark);
+    const int own = rank_below(mM) + (mark ? 0 : -1);  // entry of this lane's candidate
+    const int cfirst = __shfl((int)((uint32_t)e.x >> 3) - s0, own);
     const bool valid = (uint32_t)lane < navail;
-    int c = 0;
-    float4 ge = make_float4(0.f, 0.f, 0.f, 0.f);
-    int4 tp = make_int4(0, 0, 0, 0);
+    const int c = valid ? cfirst + lane : 0;  // lanes past the candidates read the root's record
+    rhead += (uint32_t)__popcll(__ballot(inwin && s1 <= (int)navail));
+    vhead += navail;
+
+    const float4 ge = rec[2 * (int64_t)c];
+    const int4 tp = reinterpret_cast<const int4*>(rec)[2 * (int64_t)c + 1];
     float4 fc0 = make_float4(0.f, 0.f, 0.f, 0.f), fc1 = fc0;
-    if (valid) {
-      c = (int)q[(head + lane) & qmask];
-      ge = rec[2 * (int64_t)c];
-      tp = reinterpret_cast<const int4*>(rec)[2 * (int64_t)c + 1];
-      if (LEARNED) {  // issued with the walk record: one gather latency per step, not two
-        const float4* fc = reinterpret_cast<const float4*>(T.fcell);
-        fc0 = fc[2 * (int64_t)c];
-        fc1 = fc[2 * (int64_t)c + 1];
-      }
+    if (LEARNED) {  // issued with the walk record: one gather latency per step, not two
+      const float4* fc = reinterpret_cast<const float4*>(T.fcell);
+      fc0 = fc[2 * (int64_t)c];
+      fc1 = fc[2 * (int64_t)c + 1];
     }
     bool op;
     if (LEARNED) {
@@ -257,9 +292,11 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
     } else {
       op = valid && open_cell(gmin, gmax, ge, th2);
     }
-    const bool toC = valid && !op, toL = op && tp.y == 0;
-    const int nch = (op && tp.y != 0) ? tp.y : 0;
-    const uint64_t mC = __ballot(toC), mL = __ballot(toL);
+    const bool toC = valid && !op, toL = op && tp.y == 0, toQ = op && tp.y != 0;
+    const uint64_t mC = __ballot(toC), mL = __ballot(toL), mQ = __ballot(toQ);
+    // Queue position of each opened cell's first child: prefix of the
+    // children counts (1..8) over the opened lanes, one ballot per bit.
+    const int nch = toQ ? tp.y : 0;
     int preN = 0, totN = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -267,8 +304,8 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
       preN += rank_below(m) << b;
       totN += __popcll(m) << b;
     }
-    head += navail;
-    if ((tail + (uint32_t)totN) - head > qmask + 1) return kOverflow;
+    const uint32_t nq = (uint32_t)__popcll(mQ);
+    if ((rtail + nq) - rhead > qmask + 1) return kOverflow;
     if (toC) {
       const uint32_t k = ctail + rank_below(mC);
       sh.cring[k & (kRingW - 1)] = c;
@@ -279,11 +316,11 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
       sh.lring[k & (kRingW - 1)] = make_int2(tp.z, tp.w);
       if (exp && xlb + k < xle) B.l_ids[xlb + k] = c;
     }
-    const uint32_t base = tail + preN;
-    for (int j = 0; j < nch; ++j) q[(base + j) & qmask] = tp.x + j;
+    if (toQ) q.put((rtail + rank_below(mQ)) & qmask, (tp.x << 3) | (tp.y - 1), (int)(vtail + preN));
     ctail += __popcll(mC);
     ltail += __popcll(mL);
-    tail += (uint32_t)totN;
+    rtail += nq;
+    vtail += (uint32_t)totN;
     if (gmem_q) __threadfence_block();
     wave_lds_sync();
     if (ctail - chead >= (uint32_t)kTileW) {
@@ -405,14 +442,16 @@ void walk_eval_persistent_kernel(
     V = mlp_lds(ml);
   }
   const int wv = threadIdx.x / kLanes, lane = threadIdx.x & (kLanes - 1);
-  const uint32_t qmask = (uint32_t)min(B.lds_qcap, QCAP) - 1;
+  // lds_qcap counts candidates; an entry holds up to eight
+  const uint32_t qmask = (uint32_t)min(B.lds_qcap / 8, QCAP) - 1;
+  const LQueue q{shw[wv].q};
   if constexpr (FROM_LIST) {
     for (;;) {
       const int k = take_work(B.wctr + 64 * 8, lane);
       if (k >= *src_n) break;
       const int32_t w = src[k];
-      if (walk_eval_one<PLAIN, LEARNED>(T, B, shw[wv], w, th2, eps2, acc, pot, shw[wv].q, qmask,
-                                        false, do_eval != 0, &V) == kOverflow &&
+      if (walk_eval_one<PLAIN, LEARNED>(T, B, shw[wv], w, th2, eps2, acc, pot, q, qmask, false,
+                                        do_eval != 0, &V) == kOverflow &&
           lane == 0)
         ovl[atomicAdd(ovn, 1)] = w;
     }
@@ -425,8 +464,8 @@ void walk_eval_persistent_kernel(
         const int k = take_work(B.wctr + 64 * x, lane);
         if (k >= n) break;
         const int64_t w = lo + k;
-        if (walk_eval_one<PLAIN, LEARNED>(T, B, shw[wv], w, th2, eps2, acc, pot, shw[wv].q,
-                                          qmask, false, do_eval != 0, &V) == kOverflow &&
+        if (walk_eval_one<PLAIN, LEARNED>(T, B, shw[wv], w, th2, eps2, acc, pot, q, qmask, false,
+                                          do_eval != 0, &V) == kOverflow &&
             lane == 0)
           ovl[atomicAdd(ovn, 1)] = (int32_t)w;
       }
@@ -435,14 +474,22 @@ void walk_eval_persistent_kernel(
 }
 
 // Global-memory queues: written and read by different lanes of one wave, so
-// they are accessed as volatile (no stale L1 copies) and fenced.
+// they are accessed as volatile (no stale L1 copies) and fenced.  The two
+// words of entry i sit at p[i] and p[cap + i].
 struct GQueue {
   volatile int32_t* p;
-  __device__ volatile int32_t& operator[](uint32_t i) const { return p[i]; }
+  int64_t cap;
+  __device__ int2 get(uint32_t i) const { return make_int2(p[i], p[cap + i]); }
+  __device__ void put(uint32_t i, int x, int y) const {
+    p[i] = x;
+    p[cap + i] = y;
+  }
 };
 
 // Last tier: the *src_n items of src with global-memory frontier queues of
-// 2 x (widest tree level) entries, which a breadth-first FIFO cannot exceed.
+// 2 x (widest tree level) entries, which a breadth-first FIFO cannot exceed
+// (its candidates span at most two consecutive levels, and every queued
+// entry holds at least one of them).
 template <bool PLAIN, bool LEARNED>
 __global__ __launch_bounds__(kLanes) void walk_eval_fallback_kernel(DevTree T, WalkBufs B,
                                                                     float th2, float eps2,
@@ -460,7 +507,7 @@ __global__ __launch_bounds__(kLanes) void walk_eval_fallback_kernel(DevTree T, W
     __syncthreads();
     V = mlp_lds(ml);
   }
-  GQueue q{B.gq + (int64_t)blockIdx.x * B.gq_cap};
+  GQueue q{B.gq + (int64_t)blockIdx.x * 2 * B.gq_cap, B.gq_cap};
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const int st = walk_eval_one<PLAIN, LEARNED>(T, B, sh, src[i], th2, eps2, acc, pot, q,
                                                  (uint32_t)(B.gq_cap - 1), true, do_eval != 0, &V);
@@ -488,32 +535,23 @@ int launch_walk_eval(const DevTree& T, const WalkBufs& B, float theta, float eps
   const float th2 = theta * theta, eps2 = eps * eps;
   fused_init_kernel<<<1, 64, 0, s>>>(B);
   // The breadth-first FIFO holds about two tree levels of the group's walk,
-  // which grows like theta^-3: 1024 entries hold most walks at theta >= 0.4 on
-  // 2^20-particle sets (peak ~740 at 0.5 on a Plummer sphere), 4096 the
-  // smaller angles.  Tiers: 1024-entry LDS queues (theta >= 0.37 and the
-  // learned criterion; 16, or 12 with the network, waves per CU), then the
-  // overflows with 4096-entry LDS queues (one wave per block, 7 per CU), then
-  // global-memory queues.  Below 0.37 so many walks overflow the first tier
-  // that starting with the 4096-entry queues is faster (2^20 Plummer at
-  // 0.35: 9.6 instead of 12.8 ms; 4M clumps at 0.38: 25.0 instead of 32.1).
+  // which grow like theta^-3, as entries of up to eight children: 512 entries
+  // (4 KB) held every walk of the 2^20 Plummer sphere and the 4M clumps at
+  // theta 0.3 ... 0.5.  Tiers: 512-entry LDS queues (16 waves per CU), then
+  // the overflows with 2048-entry LDS queues (one wave per block, 7 per CU),
+  // then global-memory queues.
   const bool learned = B.mlp != nullptr;
-  const bool wide = theta < 0.37f && !learned;
   auto go = [&](auto plain_tag, auto learned_tag) {
     constexpr bool P = decltype(plain_tag)::value, L = decltype(learned_tag)::value;
-    if (wide) {
-      walk_eval_persistent_kernel<P, 4096, L, 1, false><<<8 * 224, kLanes, 0, s>>>(
-          T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list2, B.ovf_count2);
-    } else {
-      if constexpr (L)  // one block of 16 waves per CU (16 x 9 KB frontiers + 12 KB network,
-                        // 159.6 KB of LDS), four per SIMD at <= 128 VGPRs
-        walk_eval_persistent_kernel<P, 1024, L, 16, false><<<8 * 32, 16 * kLanes, 0, s>>>(
-            T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list, B.ovf_count);
-      else  // 4 blocks of 4 waves per CU
-        walk_eval_persistent_kernel<P, 1024, L, 4, false><<<8 * 128, 4 * kLanes, 0, s>>>(
-            T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list, B.ovf_count);
-      walk_eval_persistent_kernel<P, 4096, L, 1, true><<<8 * 224, kLanes, 0, s>>>(
-          T, B, th2, eps2, acc, pot, do_eval, B.ovf_list, B.ovf_count, B.ovf_list2, B.ovf_count2);
-    }
+    if constexpr (L)  // one block of 16 waves per CU (16 x 9 KB frontiers + 12 KB network,
+                      // 159.6 KB of LDS), four per SIMD at <= 128 VGPRs
+      walk_eval_persistent_kernel<P, 512, L, 16, false><<<8 * 32, 16 * kLanes, 0, s>>>(
+          T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list, B.ovf_count);
+    else  // 4 blocks of 4 waves per CU
+      walk_eval_persistent_kernel<P, 512, L, 4, false><<<8 * 128, 4 * kLanes, 0, s>>>(
+          T, B, th2, eps2, acc, pot, do_eval, nullptr, nullptr, B.ovf_list, B.ovf_count);
+    walk_eval_persistent_kernel<P, 2048, L, 1, true><<<8 * 224, kLanes, 0, s>>>(
+        T, B, th2, eps2, acc, pot, do_eval, B.ovf_list, B.ovf_count, B.ovf_list2, B.ovf_count2);
     walk_eval_fallback_kernel<P, L><<<B.gq_waves, kLanes, 0, s>>>(T, B, th2, eps2, acc, pot, do_eval,
                                                                  B.ovf_list2, B.ovf_count2);
   };

@@ -46,7 +46,7 @@ def test_noalloc_equals_forces_on_two_calls(monkeypatch):
     small = W.WORKLOADS["plummer16k"]
     pos, m = W.make("plummer16k")
     T2 = og.Tree(pos, m, small["n_leaf"], 64)
-    _compare(T2, 0.3, small["eps"], monkeypatch)      # fused block path, smaller tree
+    _compare(T2, 0.3, small["eps"], monkeypatch)      # smaller tree, small angle
     _compare(T2, 0.75, small["eps"], monkeypatch)
     # frontier overflows into the global-memory queues held in the scratch
     monkeypatch.setenv("OCTGRAV_LDS_QUEUE", "64")
