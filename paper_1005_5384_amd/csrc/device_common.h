@@ -13,6 +13,22 @@ __device__ __forceinline__ int rank_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 
+// Wave-uniform copies (scalar registers) of values every lane holds alike:
+// per-item constants then stay out of the vector registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = (uint32_t)uni((int)(uint32_t)u), hi = (uint32_t)uni((int)(uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float4 uni(float4 v) {
+  return make_float4(uni(v.x), uni(v.y), uni(v.z), uni(v.w));
+}
+__device__ __forceinline__ int4 uni(int4 v) { return make_int4(uni(v.x), uni(v.y), uni(v.z), uni(v.w)); }
+
 __device__ __forceinline__ int wave_sum(int v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
@@ -144,6 +160,10 @@ __device__ __forceinline__ MacGroup mac_group(float4 gmin, float4 gmax) {
   G.gy = gmax.y - gmin.y;
   G.gz = gmax.z - gmin.z;
   G.rg = 0.5f * __builtin_amdgcn_sqrtf((G.gx * G.gx + G.gy * G.gy) + G.gz * G.gz);
+  G.gx = uni(G.gx);
+  G.gy = uni(G.gy);
+  G.gz = uni(G.gz);
+  G.rg = uni(G.rg);
   return G;
 }
 

@@ -145,53 +145,81 @@ __device__ __forceinline__ MlpView mlp_lds(const MlpLds& L) {
 // Pre-activations of one 16-sample tile t of the staged samples (xs: LDS,
 // BF16 rows of stride xss).  a1[mb][r] and a2[mb][r] are hidden unit
 // 16 mb + 4 (l/16) + r of sample 16 t + l%16.  Returns that sample's output
-// in every lane (after the fold, all four lane groups hold it).
+// in every lane (after the fold, all four lane groups hold it).  Each stage
+// issues all of its operand loads before its first product (scheduling
+// barriers keep them there), so their LDS latencies overlap instead of
+// adding up one product at a time.
 __device__ __forceinline__ float mlp_tile(const MlpView& V, const uint16_t* xs, int xss, int t,
                                           int lane, v4f32* a1, v4f32* a2) {
   const int row = lane & 15, quad = lane >> 4;
+  // Layer 1 (K = 16): four independent products.
   const v4s16 xb = load4(xs + (16 * t + row) * xss + 4 * quad);
-  uint2 h[4];  // BF16 pairs of the lane's 4 outputs per 16-row block
+  v4s16 w1[4];
+  v4f32 c1[4];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
     const float4 bb = *reinterpret_cast<const float4*>(V.b1 + 16 * mb + 4 * quad);
-    v4f32 c = {bb.x, bb.y, bb.z, bb.w};
-    const v4s16 a = load4(V.w1 + (16 * mb + row) * V.w1s + 4 * quad);
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb, c, 0, 0, 0);
-    a1[mb] = c;
-    h[mb].x = relu_pk(pk_bf16(c[0], c[1]));
-    h[mb].y = relu_pk(pk_bf16(c[2], c[3]));
+    c1[mb] = v4f32{bb.x, bb.y, bb.z, bb.w};
+    w1[mb] = load4(V.w1 + (16 * mb + row) * V.w1s + 4 * quad);
   }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) a1[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[mb], xb, c1[mb], 0, 0, 0);
+  uint2 h[4];  // BF16 pairs of the lane's 4 outputs per 16-row block
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
-    const float4 bb = *reinterpret_cast<const float4*>(V.b2 + 16 * mb + 4 * quad);
-    v4f32 c = {bb.x, bb.y, bb.z, bb.w};
+    h[mb].x = relu_pk(pk_bf16(a1[mb][0], a1[mb][1]));
+    h[mb].y = relu_pk(pk_bf16(a1[mb][2], a1[mb][3]));
+  }
+  // Layer 2 (K = 64), two 16-unit blocks at a time: two chains of two products.
+  const v4u32 b[2] = {{h[0].x, h[0].y, h[1].x, h[1].y}, {h[2].x, h[2].y, h[3].x, h[3].y}};
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const uint16_t* wr = V.w2 + (16 * mb + row) * V.w2s + 32 * q + 4 * quad;
-      const uint2 lo = *reinterpret_cast<const uint2*>(wr);
-      const uint2 hi = *reinterpret_cast<const uint2*>(wr + 16);
-      const v4u32 a = {lo.x, lo.y, hi.x, hi.y};
-      const v4u32 b = {h[2 * q].x, h[2 * q].y, h[2 * q + 1].x, h[2 * q + 1].y};
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16, a),
-                                                  __builtin_bit_cast(v8bf16, b), c, 0, 0, 0);
+  for (int half = 0; half < 2; ++half) {
+    v4u32 w2[2][2];
+    v4f32 c2[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int mb = 2 * half + k;
+      const float4 bb = *reinterpret_cast<const float4*>(V.b2 + 16 * mb + 4 * quad);
+      c2[k] = v4f32{bb.x, bb.y, bb.z, bb.w};
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const uint16_t* wr = V.w2 + (16 * mb + row) * V.w2s + 32 * q + 4 * quad;
+        const uint2 lo = *reinterpret_cast<const uint2*>(wr);
+        const uint2 hi = *reinterpret_cast<const uint2*>(wr + 16);
+        w2[k][q] = v4u32{lo.x, lo.y, hi.x, hi.y};
+      }
     }
-    a2[mb] = c;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        c2[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16, w2[k][q]),
+                                                        __builtin_bit_cast(v8bf16, b[q]), c2[k],
+                                                        0, 0, 0);
+    a2[2 * half] = c2[0];
+    a2[2 * half + 1] = c2[1];
+  }
+  // Layer 3: every row of A is w3 (same K order as layer 2).
+  v4u32 w3[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const uint2 lo = *reinterpret_cast<const uint2*>(V.w3 + 32 * q + 4 * quad);
+    const uint2 hi = *reinterpret_cast<const uint2*>(V.w3 + 32 * q + 16 + 4 * quad);
+    w3[q] = v4u32{lo.x, lo.y, hi.x, hi.y};
   }
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
     h[mb].x = relu_pk(pk_bf16(a2[mb][0], a2[mb][1]));
     h[mb].y = relu_pk(pk_bf16(a2[mb][2], a2[mb][3]));
   }
-  // Layer 3: every row of A is w3 (same K order as layer 2).
   v4f32 y = {V.b3, V.b3, V.b3, V.b3};
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const uint2 lo = *reinterpret_cast<const uint2*>(V.w3 + 32 * q + 4 * quad);
-    const uint2 hi = *reinterpret_cast<const uint2*>(V.w3 + 32 * q + 16 + 4 * quad);
-    const v4u32 a = {lo.x, lo.y, hi.x, hi.y};
-    const v4u32 b = {h[2 * q].x, h[2 * q].y, h[2 * q + 1].x, h[2 * q + 1].y};
-    y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16, a),
-                                                __builtin_bit_cast(v8bf16, b), y, 0, 0, 0);
+    const v4u32 bq = {h[2 * q].x, h[2 * q].y, h[2 * q + 1].x, h[2 * q + 1].y};
+    y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16, w3[q]),
+                                                __builtin_bit_cast(v8bf16, bq), y, 0, 0, 0);
   }
   return y[0];
 }

@@ -174,11 +174,18 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
                               float* __restrict__ pot, Q q, uint32_t qmask, bool gmem_q,
                               bool do_eval, int cw, int* nband_out, const MlpView* mv) {
   const int lane = threadIdx.x & (kLanes - 1);
-  const int2 wk = reinterpret_cast<const int2*>(T.work)[w];
+  // Per-item constants; with the learned criterion they are held in scalar
+  // registers (its network needs the vector registers).
+  auto U = [](auto v) {
+    if constexpr (LEARNED) return uni(v);
+    else return v;
+  };
+  const int2 wk0 = reinterpret_cast<const int2*>(T.work)[w];
+  const int2 wk = make_int2(U(wk0.x), U(wk0.y));
   const int64_t g = wk.x;
-  const int4 gi = reinterpret_cast<const int4*>(T.ginfo)[g];
+  const int4 gi = U(reinterpret_cast<const int4*>(T.ginfo)[g]);
   const float4* gbox = reinterpret_cast<const float4*>(T.gbox);
-  const float4 gmin = gbox[2 * g], gmax = gbox[2 * g + 1];
+  const float4 gmin = U(gbox[2 * g]), gmax = U(gbox[2 * g + 1]);
   const float4* rec = reinterpret_cast<const float4*>(T.wrec);
 
   WItem<PLAIN, SH> it{T, sh, eps2};
@@ -195,12 +202,12 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
   const bool exp = B.export_lists && wk.y == 0;
   // learned criterion state
   const bool trace = LEARNED && B.tr_s != nullptr && wk.y == 0;
-  const int64_t trb = trace ? B.tr_off[g] : 0, tre = trace ? B.tr_off[g + 1] : 0;
+  const int64_t trb = trace ? U(B.tr_off[g]) : 0, tre = trace ? U(B.tr_off[g + 1]) : 0;
   const MacGroup mg = mac_group(gmin, gmax);
   double sum2 = 0.0;
   int nband = 0;
-  const int64_t xcb = exp ? B.c_off[g] : 0, xce = exp ? B.c_off[g + 1] : 0;
-  const int64_t xlb = exp ? B.l_off[g] : 0, xle = exp ? B.l_off[g + 1] : 0;
+  const int64_t xcb = exp ? U(B.c_off[g]) : 0, xce = exp ? U(B.c_off[g + 1]) : 0;
+  const int64_t xlb = exp ? U(B.l_off[g]) : 0, xle = exp ? U(B.l_off[g + 1]) : 0;
 
   // Frontier: entries [rhead, rtail) of q; candidates [vhead, vtail) of the
   // item's breadth-first sequence (the entry at rhead may be partly taken).
@@ -225,57 +232,117 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
   if (gmem_q) __threadfence_block();  // queue stores complete before other lanes read
   wave_lds_sync();
 
-  while (vhead < vtail) {
-    const uint32_t nent = min((uint32_t)kLanes, rtail - rhead);
-    const uint32_t navail = min((uint32_t)kLanes, vtail - vhead);
+  // Candidate of each lane for the next min(64, vtail - vh) candidates from
+  // position vh, whose entry is rh; *used = entries that window uses up.
+  auto take = [&](uint32_t rh, uint32_t vh, uint32_t* used) {
+    const uint32_t nent = min((uint32_t)kLanes, rtail - rh);
+    const uint32_t navail = min((uint32_t)kLanes, vtail - vh);
     const bool inq = (uint32_t)lane < nent;
     int2 e = make_int2(0, 0);
-    if (inq) e = q.get((rhead + lane) & qmask);
-    // First lane of this entry's children in the step (<= 0 for the partly
+    if (inq) e = q.get((rh + lane) & qmask);
+    // First lane of this entry's children in the window (<= 0 for a partly
     // taken head entry) and one past its last.
-    const int s0 = (int)((uint32_t)e.y - vhead);
+    const int s0 = (int)((uint32_t)e.y - vh);
     const int s1 = s0 + (int)((uint32_t)e.x & 7u) + 1;
     const bool inwin = inq && s0 < kLanes;
-    const int stamp = -1 - (int)vhead;
+    const int stamp = -1 - (int)vh;
     if (inwin) sh.lfirst[max(s0, 0)] = stamp;
     wave_lds_sync();
     const bool mark = sh.lfirst[lane] == stamp;
     const uint64_t mM = __ballot(mark);
     const int own = rank_below(mM) + (mark ? 0 : -1);  // entry of this lane's candidate
     const int cfirst = __shfl((int)((uint32_t)e.x >> 3) - s0, own);
+    *used = (uint32_t)__popcll(__ballot(inwin && s1 <= (int)navail));
+    // lanes past the candidates read the root's record
+    return (uint32_t)lane < navail ? cfirst + lane : 0;
+  };
+  // Learned criterion: a step that runs the network also scores the next
+  // step's band candidates when all of them are queued already (they come
+  // before anything this step queues), so one network call serves two steps
+  // with fuller tiles; the next step then reuses the candidates, tests and
+  // scores kept here.
+  bool have_next = false;
+  int c_next = 0;
+  float y_next = 0.0f;
+  uint32_t used_next = 0;
+  uint64_t mO_next = 0, mB_next = 0;
+
+  while (vhead < vtail) {
+    const uint32_t navail = min((uint32_t)kLanes, vtail - vhead);
     const bool valid = (uint32_t)lane < navail;
-    const int c = valid ? cfirst + lane : 0;  // lanes past the candidates read the root's record
-    rhead += (uint32_t)__popcll(__ballot(inwin && s1 <= (int)navail));
+    int c;
+    uint32_t used;
+    if (LEARNED && have_next) {
+      c = c_next;
+      used = used_next;
+    } else {
+      c = take(rhead, vhead, &used);
+    }
+    rhead += used;
     vhead += navail;
 
-    const float4 ge = rec[2 * (int64_t)c];
     const int4 tp = reinterpret_cast<const int4*>(rec)[2 * (int64_t)c + 1];
-    float4 fc0 = make_float4(0.f, 0.f, 0.f, 0.f), fc1 = fc0;
-    if (LEARNED) {  // issued with the walk record: one gather latency per step, not two
-      const float4* fc = reinterpret_cast<const float4*>(T.fcell);
-      fc0 = fc[2 * (int64_t)c];
-      fc1 = fc[2 * (int64_t)c + 1];
-    }
     bool op;
     if (LEARNED) {
-      const bool olo = valid && open_cell(gmin, gmax, ge, B.mac_lo2);
-      const bool band = olo && !open_cell(gmin, gmax, ge, B.mac_hi2);
-      const uint64_t mB = __ballot(band);
-      bool accb = false;
-      if (mB) {
-        // Band lanes stage their features as consecutive rows; the network
-        // runs on ceil(rows / 16) tiles and each lane picks its row's output.
-        const int rk = rank_below(mB);
-        uint16_t* xs = reinterpret_cast<uint16_t*>(sh.tile);
-        if (band) {
-          float f[kMlpIn];
-          mac_features(mg, ge, fc0, fc1, f);
-          mlp_stage(xs, kXsLd, rk, f);
+      bool olo, band, accb = false;
+      uint64_t mB;
+      float yh = 0.0f;
+      uint16_t* xs = reinterpret_cast<uint16_t*>(sh.tile);
+      if (have_next) {
+        have_next = false;
+        olo = (mO_next >> lane) & 1;
+        band = (mB_next >> lane) & 1;
+        mB = mB_next;
+        yh = y_next;
+      } else {
+        const float4* fc = reinterpret_cast<const float4*>(T.fcell);
+        {
+          const float4 ge = rec[2 * (int64_t)c];
+          const float4 fc0 = fc[2 * (int64_t)c], fc1 = fc[2 * (int64_t)c + 1];
+          olo = valid && open_cell(gmin, gmax, ge, B.mac_lo2);
+          band = olo && !open_cell(gmin, gmax, ge, B.mac_hi2);
+          mB = __ballot(band);
+          // Band lanes stage their features as consecutive rows.
+          if (band) {
+            float f[kMlpIn];
+            mac_features(mg, ge, fc0, fc1, f);
+            mlp_stage(xs, kXsLd, rank_below(mB), f);
+          }
         }
-        wave_lds_sync();
-        const float yrow = mlp_scores(*mv, xs, kXsLd, lane, (__popcll(mB) + 15) >> 4);
-        wave_lds_sync();
-        const float yh = __shfl(yrow, rk);
+        if (mB) {
+          const int ra = __popcll(mB);
+          int rows = ra;
+          if (vtail - vhead >= (uint32_t)kLanes) {  // the next step's 64 candidates are queued
+            uint32_t u2;
+            const int c2 = take(rhead, vhead, &u2);
+            const float4 ge = rec[2 * (int64_t)c2];
+            const float4 fc0 = fc[2 * (int64_t)c2], fc1 = fc[2 * (int64_t)c2 + 1];
+            const bool olo2 = open_cell(gmin, gmax, ge, B.mac_lo2);
+            const bool band2 = olo2 && !open_cell(gmin, gmax, ge, B.mac_hi2);
+            const uint64_t mB2 = __ballot(band2);
+            if (ra + __popcll(mB2) <= kLanes) {  // every row's score lands in its own lane
+              if (band2) {
+                float f[kMlpIn];
+                mac_features(mg, ge, fc0, fc1, f);
+                mlp_stage(xs, kXsLd, ra + rank_below(mB2), f);
+              }
+              rows += __popcll(mB2);
+              have_next = true;
+              c_next = c2;
+              used_next = u2;
+              mO_next = __ballot(olo2);
+              mB_next = mB2;
+            }
+          }
+          // The network runs on ceil(rows / 16) tiles; lane l receives row l's output.
+          wave_lds_sync();
+          const float yrow = mlp_scores(*mv, xs, kXsLd, lane, (rows + 15) >> 4);
+          wave_lds_sync();
+          yh = __shfl(yrow, rank_below(mB));
+          if (have_next) y_next = __shfl(yrow, ra + rank_below(mB_next));
+        }
+      }
+      if (mB) {
         accb = band && yh <= B.mac_ltau;
         // 10^(2 y) = 2^(2 log2(10) y) on the FP32 exp unit; summed in FP64
         if (accb) sum2 += (double)__builtin_amdgcn_exp2f(yh * 6.64385618977472f);
@@ -290,6 +357,7 @@ __device__ int walk_eval_item(const DevTree& T, const WalkBufs& B, SH& sh, int64
       }
       op = olo && !accb;
     } else {
+      const float4 ge = rec[2 * (int64_t)c];
       op = valid && open_cell(gmin, gmax, ge, th2);
     }
     const bool toC = valid && !op, toL = op && tp.y == 0, toQ = op && tp.y != 0;
@@ -412,7 +480,7 @@ __device__ int walk_eval_one(const DevTree& T, const WalkBufs& B, SH& sh, int64_
 __device__ __forceinline__ int take_work(int32_t* ctr, int lane) {
   int k = 0;
   if (lane == 0) k = atomicAdd(ctr, 1);
-  return __shfl(k, 0);
+  return uni(__shfl(k, 0));
 }
 
 // Persistent blocks of NW independent waves (with the learned criterion
