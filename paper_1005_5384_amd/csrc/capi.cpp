@@ -150,7 +150,11 @@ struct octgrav_tree : DevAlloc {
   int fetch_host_arrays() {
     if (!host_partial) return OCTGRAV_OK;
     const int64_t n = h.n, nc = h.n_cells();
+    const int64_t ng = h.n_groups(), nw = h.n_work();
     h.perm.resize(n);
+    h.depth.resize(nc);
+    h.groups.resize(ng);
+    h.work.resize((size_t)nw * 2);
     h.topo.resize((size_t)nc * 4);
     h.geo.resize((size_t)nc * 4);
     h.mp.resize((size_t)nc * 12);
@@ -161,7 +165,10 @@ struct octgrav_tree : DevAlloc {
         hipMemcpy(h.geo.data(), darr.geo_host, (size_t)nc * 16, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(h.mp.data(), dt.mp, (size_t)nc * 48, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(h.mp64.data(), darr.mp64, (size_t)nc * 80, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(h.box.data(), darr.box, (size_t)nc * 48, hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(h.box.data(), darr.box, (size_t)nc * 48, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(h.depth.data(), darr.depth, (size_t)nc * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        (ng > 0 && hipMemcpy(h.groups.data(), darr.groups, (size_t)ng * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+        (nw > 0 && hipMemcpy(h.work.data(), dt.work, (size_t)nw * 8, hipMemcpyDeviceToHost) != hipSuccess))
       return fail(OCTGRAV_EHIP, "tree copy-back failed");
     host_partial = false;
     return OCTGRAV_OK;
@@ -202,7 +209,7 @@ struct octgrav_tree : DevAlloc {
   }
 
   int to_device() {
-    const int64_t n = h.n, nc = h.n_cells(), ng = h.n_groups(), nw = (int64_t)h.work.size() / 2;
+    const int64_t n = h.n, nc = h.n_cells(), ng = h.n_groups(), nw = h.n_work();
     dt.n = n;
     dt.nc = nc;
     dt.ng = ng;
@@ -289,7 +296,7 @@ struct octgrav_tree : DevAlloc {
   // Walk and list buffers, scratch, events and the evaluation stream (after
   // the tree arrays are on the device, from either build).
   int alloc_walk_buffers() {
-    const int64_t n = h.n, ng = h.n_groups(), nw = (int64_t)h.work.size() / 2;
+    const int64_t n = h.n, ng = h.n_groups(), nw = h.n_work();
     if (dt.nc >= (int64_t(1) << 29))  // the walks' queue entries hold cell id << 3
       return fail(OCTGRAV_EINVAL, "tree has " + std::to_string(dt.nc) +
                                       " cells; the walks address at most 2^29 - 1");
@@ -341,8 +348,7 @@ struct octgrav_tree : DevAlloc {
         return fail(OCTGRAV_EHIP, "hipEventCreate failed");
     if (!eval_stream && hipStreamCreateWithFlags(&eval_stream, hipStreamNonBlocking) != hipSuccess)
       return fail(OCTGRAV_EHIP, "hipStreamCreate failed");
-    gwork.assign(ng + 1, nw);
-    for (int64_t w = nw - 1; w >= 0; --w) gwork[h.work[2 * w]] = w;
+    gwork.clear();  // built on first use (group_work)
     dev = true;
     return OCTGRAV_OK;
   }
@@ -384,7 +390,23 @@ struct octgrav_tree : DevAlloc {
   // evaluation, which waits only for that batch's lists.  Needs list buffers
   // sized by an earlier call; a group whose lists do not fit is skipped and
   // reported through the totals, and the caller redoes the call.
+  // First work item of every group (and nw at [ng]), from the host's work
+  // list, fetched from the device for a device-built tree.
+  int group_work() {
+    const int64_t ng = h.n_groups(), nw = h.n_work();
+    if ((int64_t)gwork.size() == ng + 1) return OCTGRAV_OK;
+    if ((int64_t)h.work.size() != 2 * nw) {
+      h.work.resize((size_t)nw * 2);
+      if (nw > 0 && hipMemcpy(h.work.data(), dt.work, (size_t)nw * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(OCTGRAV_EHIP, "work list copy failed");
+    }
+    gwork.assign(ng + 1, nw);
+    for (int64_t w = nw - 1; w >= 0; --w) gwork[h.work[2 * w]] = w;
+    return OCTGRAV_OK;
+  }
+
   int two_pass_pipelined(float theta, float eps, bool plain, float* acc, float* pot) {
+    if (int rc = group_work()) return rc;
     const int64_t ng = h.n_groups();
     const int nb = (int)std::min<int64_t>(kBatches, std::max<int64_t>(1, ng / 256));
     WalkBufs ws = wb;  // slotted lists: no offsets scan between the walk and the evaluation
@@ -520,7 +542,7 @@ int octgrav_tree_stats(const octgrav_tree* t, octgrav_stats* s) {
   s->n_groups = h.n_groups();
   s->max_depth = h.max_depth;
   s->max_level_cells = h.max_level_cells;
-  s->n_work = (int64_t)h.work.size() / 2;
+  s->n_work = h.n_work();
   s->n_leaf = h.n_leaf;
   s->n_group = h.n_group;
   return OCTGRAV_OK;
@@ -733,7 +755,7 @@ int octgrav_forces_noalloc(octgrav_tree* t, float theta, float eps, float* acc, 
     // Carve the per-call scratch of the fused walk + evaluation (and of the
     // diagnostics' partial sums) out of the array: fixed parts first, then as
     // many fallback frontier queues as fit (at least one).
-    const int64_t ng = t->h.n_groups(), nw = (int64_t)t->h.work.size() / 2;
+    const int64_t ng = t->h.n_groups(), nw = t->h.n_work();
     size_t off = 0;
     auto take = [&](size_t bytes) {
       const size_t at = off;

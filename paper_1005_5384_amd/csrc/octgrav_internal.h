@@ -30,8 +30,12 @@ struct HostTree {
   std::vector<int32_t> ginfo;    // [ng*4] first, n, cell, 0
   std::vector<float> gbox;       // [ng*8] gmin xyz 0, gmax xyz 0
   std::vector<int32_t> work;     // [nw*2] group, first target offset within group
-  int64_t n_cells() const { return (int64_t)depth.size(); }
-  int64_t n_groups() const { return (int64_t)groups.size(); }
+  // Counts of a device build whose depth / groups / work arrays stay on the
+  // device until an export fetches them (-1: the vectors' sizes).
+  int64_t nc_dev = -1, ng_dev = -1, nw_dev = -1;
+  int64_t n_cells() const { return nc_dev >= 0 ? nc_dev : (int64_t)depth.size(); }
+  int64_t n_groups() const { return ng_dev >= 0 ? ng_dev : (int64_t)groups.size(); }
+  int64_t n_work() const { return nw_dev >= 0 ? nw_dev : (int64_t)work.size() / 2; }
 };
 
 // Builds the host tree; returns false with a message on bad input.
@@ -161,9 +165,10 @@ int launch_mlp_adam(float* P, float* m, float* v, const float* g, float lr, floa
 // Device tree build (same result as build_host_tree, computed on the GPU).
 // The persistent arrays are allocated through DevAlloc (owned by the
 // caller); DeviceArrays receives the FP64 boxes / moments, the unsigned
-// boundary image and the depths, which stay on the device.  Fills h with the
-// scalars and the small host arrays (depth, groups, work); the topology stays
-// on the device with the rest.
+// boundary image, the depths and the group cells, which stay on the device.
+// Fills h with the scalars and the counts (nc_dev, ng_dev, nw_dev); every
+// array stays on the device.  A build with pools makes two host round trips
+// (the level counts, then the group and work counts).
 struct DevAlloc {
   virtual int alloc(void** p, size_t bytes) = 0;
   virtual ~DevAlloc() = default;
@@ -187,12 +192,18 @@ struct SeqPool {
 struct BuildPools {
   SeqPool outer, level, cells;
   int last_levels = 0;  // non-empty levels of the previous build (0: unknown)
+  void* pinned = nullptr;  // page-locked host copy of the build's scalars (tree_gpu.hip)
+  BuildPools() = default;
+  BuildPools(const BuildPools&) = delete;
+  BuildPools& operator=(const BuildPools&) = delete;
+  ~BuildPools();
 };
 struct DeviceArrays {
   const double* box = nullptr;     // [nc * 6]
   const double* mp64 = nullptr;    // [nc * 10]
   const float* geo_host = nullptr; // [nc * 4]
   const int32_t* depth = nullptr;  // [nc]
+  const int32_t* groups = nullptr; // [ng]
 };
 // Inputs are host arrays (copied) or, with inputs_on_device, device arrays
 // (checked on the device).

@@ -13,6 +13,8 @@
 // particle and compacted, which orders them by first particle) and the work
 // chunks.
 #include <hip/hip_runtime.h>
+
+#include <cstddef>
 #include <hipcub/hipcub.hpp>
 
 #include <cmath>
@@ -55,6 +57,36 @@ __global__ void bbox_kernel(const float* __restrict__ pos, int64_t n, float* __r
   if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// Root cube from the bounding-box partials with the host's rules (block
+// partials reduced in block order keeping the earlier of equal values; the
+// cube of the largest extent rounded up to a power of two, centred on the
+// box; FP64, the same operations): cube = corner xyz, side, grid step, 1 / step.
+__global__ void root_kernel(const float* __restrict__ part, int nbb, double* __restrict__ cube) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0) return;
+  double lo[3], hi[3];
+  for (int k = 0; k < 3; ++k) {
+    float a = part[k], b = part[3 + k];
+    for (int i = 1; i < nbb; ++i) {
+      const float x = part[6 * i + k], y = part[6 * i + 3 + k];
+      a = x < a ? x : a;
+      b = b < y ? y : b;
+    }
+    lo[k] = a;
+    hi[k] = b;
+  }
+  const double e1 = hi[1] - lo[1], e2 = hi[2] - lo[2], e0 = hi[0] - lo[0];
+  const double e12 = e1 < e2 ? e2 : e1;
+  const double ext = e0 < e12 ? e12 : e0;
+  int e = 1;
+  if (ext > 0) (void)frexp(ext, &e);
+  const double side = ext > 0 ? ldexp(1.0, e) : 1.0;
+  for (int k = 0; k < 3; ++k) cube[k] = (lo[k] + hi[k]) * 0.5 - 0.5 * side;
+  cube[3] = side;
+  cube[4] = ldexp(side, -kMaxDepth);
+  cube[5] = ldexp(1.0 / side, kMaxDepth);
+}
+
 // Input check of device-resident inputs: bit 1 = a position not finite or
 // |x| >= 2^60, bit 2 = a mass not finite or not > 0.
 __global__ void validate_kernel(const float* __restrict__ pos, const float* __restrict__ mass,
@@ -93,14 +125,16 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
   return x;
 }
 
-__global__ void keys_kernel(const float* __restrict__ pos, int64_t n, double cx, double cy,
-                            double cz, double step, double inv, uint64_t* __restrict__ key,
+// cube: corner xyz, side, grid step, 1 / step (root_kernel).
+__global__ void keys_kernel(const float* __restrict__ pos, int64_t n,
+                            const double* __restrict__ cube, uint64_t* __restrict__ key,
                             int32_t* __restrict__ idx) {
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (i >= n) return;
-  const uint32_t u0 = grid_coord((double)pos[3 * i], cx, step, inv);
-  const uint32_t u1 = grid_coord((double)pos[3 * i + 1], cy, step, inv);
-  const uint32_t u2 = grid_coord((double)pos[3 * i + 2], cz, step, inv);
+  const double step = cube[4], inv = cube[5];
+  const uint32_t u0 = grid_coord((double)pos[3 * i], cube[0], step, inv);
+  const uint32_t u1 = grid_coord((double)pos[3 * i + 1], cube[1], step, inv);
+  const uint32_t u2 = grid_coord((double)pos[3 * i + 2], cube[2], step, inv);
   key[i] = spread3(u0) | spread3(u1) << 1 | spread3(u2) << 2;
   idx[i] = (int32_t)i;
 }
@@ -538,10 +572,28 @@ __global__ void group_fill_kernel(const int32_t* __restrict__ at, const int32_t*
 }
 
 __global__ void work_kernel(const int32_t* __restrict__ nchunk, const int32_t* __restrict__ pre,
-                            int64_t ng, int2* __restrict__ work) {
+                            const int32_t* __restrict__ ngp, int2* __restrict__ work) {
   const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (g >= ng) return;
+  if (g >= *ngp) return;
   for (int k = 0; k < nchunk[g]; ++k) work[pre[g] + k] = make_int2((int32_t)g, k * kChunk);
+}
+
+// The build's scalars the host needs, gathered in one place on the device so
+// that one copy fetches them.
+struct BuildInfo {
+  Level lv[kMaxDepth + 2];
+  double cube[6];  // root_kernel
+  int32_t bad;     // validate_kernel
+  int32_t ng, nw, leaves;
+};
+
+__global__ void counts_kernel(const int32_t* __restrict__ ngp, const int32_t* __restrict__ nwp,
+                              const int32_t* __restrict__ nleaf, BuildInfo* __restrict__ info) {
+  if (threadIdx.x == 0) {
+    info->ng = *ngp;
+    info->nw = *nwp;
+    info->leaves = *nleaf;
+  }
 }
 
 // Scratch allocations of one build: fresh ones freed on every exit, or slots
@@ -609,6 +661,10 @@ SeqPool::~SeqPool() {
     if (q) hipFree(q);
 }
 
+BuildPools::~BuildPools() {
+  if (pinned) hipHostFree(pinned);
+}
+
 int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_device, int64_t n,
                       int n_leaf, int n_group, HostTree& h, DevTree& dt, DeviceArrays& out,
                       DevAlloc& alloc, void* stream, std::string& err, BuildPools* pools) {
@@ -628,10 +684,32 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   h.n_leaf = n_leaf;
   h.n_group = n_group;
 
+  // The scalars the host needs come back in two copies (after the levels,
+  // after the groups), into page-locked memory kept with the pools.
+  BuildInfo* info = S.get<BuildInfo>(1);
+  if (!info) return fail("device allocation failed");
+  BuildInfo local;
+  BuildInfo* hinfo = &local;
+  if (pools) {
+    if (!pools->pinned && hipHostMalloc(&pools->pinned, sizeof(BuildInfo)) != hipSuccess) {
+      (void)hipGetLastError();
+      pools->pinned = nullptr;
+    }
+    if (pools->pinned) hinfo = static_cast<BuildInfo*>(pools->pinned);
+  }
+  auto fetch = [&](size_t off, size_t bytes) {
+    return hipMemcpyAsync(reinterpret_cast<char*>(hinfo) + off, reinterpret_cast<char*>(info) + off,
+                          bytes, hipMemcpyDeviceToHost, s) == hipSuccess &&
+           hipStreamSynchronize(s) == hipSuccess;
+  };
+
   // Inputs on the device (copied there, or checked there: finite positions
-  // with |x| < 2^60 and finite masses > 0, as the host build requires).
+  // with |x| < 2^60 and finite masses > 0, as the host build requires; the
+  // verdict comes back with the level counts, and every kernel before that
+  // is safe on any input values).
   const float* pos = pos_in;
   const float* mass = mass_in;
+  if (hipMemsetAsync(&info->bad, 0, 4, s) != hipSuccess) return fail("memset failed");
   if (!inputs_on_device) {
     float* p = S.get<float>(3 * n);
     float* q = S.get<float>(n);
@@ -642,16 +720,7 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
     pos = p;
     mass = q;
   } else {
-    int32_t* bad = S.get<int32_t>(1);
-    if (!bad) return fail("device allocation failed");
-    int32_t hb = 0;
-    if (hipMemsetAsync(bad, 0, 4, s) != hipSuccess) return fail("memset failed");
-    validate_kernel<<<std::min<int64_t>(2048, blocks(n)), kT, 0, s>>>(pos, mass, n, bad);
-    if (hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return fail("input check failed");
-    if (hb & 1) return fail("positions must be finite with |x| < 2^60");
-    if (hb & 2) return fail("masses must be finite and > 0");
+    validate_kernel<<<std::min<int64_t>(2048, blocks(n)), kT, 0, s>>>(pos, mass, n, &info->bad);
   }
 
   // Root cube (the host's rule on the device's bounding box).
@@ -659,31 +728,15 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   float* bbp = S.get<float>(6 * nbb);
   if (!bbp) return fail("device allocation failed");
   bbox_kernel<<<nbb, kT, 0, s>>>(pos, n, bbp);
-  std::vector<float> bbh((size_t)6 * nbb);
-  if (hipMemcpyAsync(bbh.data(), bbp, bbh.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return fail("bounding box failed");
-  double lo[3], hi[3];
-  for (int k = 0; k < 3; ++k) {
-    float a = bbh[k], b = bbh[3 + k];
-    for (int i = 1; i < nbb; ++i) {
-      a = std::min(a, bbh[6 * i + k]);
-      b = std::max(b, bbh[6 * i + 3 + k]);
-    }
-    lo[k] = a;
-    hi[k] = b;
-  }
-  root_cube(lo, hi, h.corner, &h.side);
+  root_kernel<<<1, 64, 0, s>>>(bbp, nbb, info->cube);
 
   // Keys and the stable sort (ties keep the input order).
-  const double step = std::ldexp(h.side, -kMaxDepth), inv = std::ldexp(1.0 / h.side, kMaxDepth);
   uint64_t* key = S.get<uint64_t>(n);
   uint64_t* key2 = S.get<uint64_t>(n);
   int32_t* idx = S.get<int32_t>(n);
   int32_t* perm = nullptr;
   if (!key || !key2 || !idx || alloc.alloc((void**)&perm, (size_t)n * 4)) return fail("device allocation failed");
-  keys_kernel<<<blocks(n), kT, 0, s>>>(pos, n, h.corner[0], h.corner[1], h.corner[2], step, inv,
-                                       key, idx);
+  keys_kernel<<<blocks(n), kT, 0, s>>>(pos, n, info->cube, key, idx);
   size_t sbytes = 0;
   if (hipcub::DeviceRadixSort::SortPairs(nullptr, sbytes, key, key2, idx, perm, (int)n, 0, 63, s) !=
       hipSuccess)
@@ -721,15 +774,15 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   // trip per level); a tree that outgrows the cell arrays is redone below
   // level by level, growing them.
   {
-    Level* lv = S.get<Level>(kMaxDepth + 2);
+    Level* lv = info->lv;
     int32_t* nkid = S.get<int32_t>(cap);
     int32_t* bsum = S.get<int32_t>(kLB);
-    if (!lv || !nkid || !bsum) return fail("device allocation failed");
+    if (!nkid || !bsum) return fail("device allocation failed");
     level_init_kernel<<<1, 64, 0, s>>>(C, lv, (int32_t)n);
     // A rebuild launches the levels its previous tree had plus two, then
     // looks whether the next one is empty (an empty level still costs three
-    // launches); the rest follow only if the tree turned out deeper.
-    std::vector<Level> hl(kMaxDepth + 2);
+    // launches); the rest follow only if the tree turned out deeper.  The
+    // copy also brings the input check and the root cube.
     int L0 = 0, L1 = kMaxDepth;
     if (pools && pools->last_levels > 0) L1 = std::min(kMaxDepth, pools->last_levels + 1);
     for (;;) {
@@ -738,23 +791,24 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
         level_scan_kernel<<<1, kT, 0, s>>>(bsum, lv, L, cap);
         emit_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum);
       }
-      if (hipMemcpyAsync(hl.data(), lv, hl.size() * sizeof(Level), hipMemcpyDeviceToHost, s) !=
-              hipSuccess ||
-          hipStreamSynchronize(s) != hipSuccess)
-        return fail("subdivision failed");
-      if (L1 == kMaxDepth || hl[L1 + 1].end == hl[L1 + 1].beg) break;
+      if (!fetch(0, offsetof(BuildInfo, ng))) return fail("subdivision failed");
+      if (hinfo->bad & 1) return fail("positions must be finite with |x| < 2^60");
+      if (hinfo->bad & 2) return fail("masses must be finite and > 0");
+      if (L1 == kMaxDepth || hinfo->lv[L1 + 1].end == hinfo->lv[L1 + 1].beg) break;
       L0 = L1 + 1;
       L1 = kMaxDepth;
     }
+    for (int k = 0; k < 3; ++k) h.corner[k] = hinfo->cube[k];
+    h.side = hinfo->cube[3];
     bool over = false;
-    for (const Level& v : hl) over = over || v.overflow;
+    for (const Level& v : hinfo->lv) over = over || v.overflow;
     if (!over) {
       int levels = 0;
-      for (int L = 0; L <= kMaxDepth && hl[L].end > hl[L].beg; ++L) {
-        h.max_level_cells = std::max(h.max_level_cells, hl[L].end - hl[L].beg);
-        if (hl[L].total > 0) h.max_depth = L + 1;
-        level_beg.push_back(hl[L].end);
-        lbeg = lend = hl[L].end;
+      for (int L = 0; L <= kMaxDepth && hinfo->lv[L].end > hinfo->lv[L].beg; ++L) {
+        h.max_level_cells = std::max(h.max_level_cells, hinfo->lv[L].end - hinfo->lv[L].beg);
+        if (hinfo->lv[L].total > 0) h.max_depth = L + 1;
+        level_beg.push_back(hinfo->lv[L].end);
+        lbeg = lend = hinfo->lv[L].end;
         levels = L + 1;
       }
       if (pools) pools->last_levels = levels;
@@ -829,7 +883,10 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   if (hipMemcpyAsync(depth, C.depth, (size_t)nc * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail("copy failed");
 
-  // Groups and work chunks.
+  // Groups and work chunks, sized by bounds known here (groups <= cells,
+  // work items <= groups + n / kChunk), so that their counts come back in
+  // one copy at the end.
+  const int64_t ngcap = nc, nwcap = nc + n / kChunk + 1;
   int32_t* at = S.get<int32_t>(n);
   int32_t* f = S.get<int32_t>(n + 1);
   int32_t* fpre = S.get<int32_t>(n + 1);
@@ -839,43 +896,28 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   flag_kernel<<<blocks(n), kT, 0, s>>>(at, n, f);
   if (hipMemsetAsync(f + n, 0, 4, s) != hipSuccess) return fail("memset failed");
   if (exclusive_sum(f, fpre, n + 1, S, s)) return fail("scan failed");
-  int32_t ng = 0;
-  if (hipMemcpyAsync(&ng, fpre + n, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return fail("group count failed");
   int32_t* groups = nullptr;
   int4* ginfo = nullptr;
   float4* gbox = nullptr;
-  if (!A((void**)&groups, (size_t)ng * 4) || !A((void**)&ginfo, (size_t)ng * 16) ||
-      !A((void**)&gbox, (size_t)ng * 32))
-    return fail("device allocation failed");
-  int32_t* nchunk = S.get<int32_t>(ng + 1);
-  int32_t* cpre = S.get<int32_t>(ng + 1);
-  if (!nchunk || !cpre) return fail("device allocation failed");
-  group_fill_kernel<<<blocks(n), kT, 0, s>>>(at, f, fpre, n, C, box, groups, ginfo, gbox, nchunk);
-  if (hipMemsetAsync(nchunk + ng, 0, 4, s) != hipSuccess) return fail("memset failed");
-  if (exclusive_sum(nchunk, cpre, (int64_t)ng + 1, S, s)) return fail("scan failed");
-  int32_t nw = 0;
-  if (hipMemcpyAsync(&nw, cpre + ng, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return fail("work count failed");
   int2* work = nullptr;
-  if (!A((void**)&work, (size_t)nw * 8)) return fail("device allocation failed");
-  work_kernel<<<blocks(ng), kT, 0, s>>>(nchunk, cpre, ng, work);
-
-  // Host copies the rest of the library needs now (the remaining arrays are
-  // fetched on export).
-  h.depth.resize(nc);
-  h.groups.resize(ng);
-  h.work.resize((size_t)nw * 2);
-  int32_t leaves = 0;
-  if (hipMemcpyAsync(h.depth.data(), depth, (size_t)nc * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(&leaves, nleaf, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(h.groups.data(), groups, (size_t)ng * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(h.work.data(), work, (size_t)nw * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return fail("host copies failed");
-  h.n_leaves = leaves;
+  if (!A((void**)&groups, (size_t)ngcap * 4) || !A((void**)&ginfo, (size_t)ngcap * 16) ||
+      !A((void**)&gbox, (size_t)ngcap * 32) || !A((void**)&work, (size_t)nwcap * 8))
+    return fail("device allocation failed");
+  int32_t* nchunk = S.get<int32_t>(ngcap + 1);
+  int32_t* cpre = S.get<int32_t>(ngcap + 1);
+  if (!nchunk || !cpre) return fail("device allocation failed");
+  if (hipMemsetAsync(nchunk, 0, (size_t)(ngcap + 1) * 4, s) != hipSuccess) return fail("memset failed");
+  group_fill_kernel<<<blocks(n), kT, 0, s>>>(at, f, fpre, n, C, box, groups, ginfo, gbox, nchunk);
+  if (exclusive_sum(nchunk, cpre, ngcap + 1, S, s)) return fail("scan failed");
+  work_kernel<<<blocks(ngcap), kT, 0, s>>>(nchunk, cpre, fpre + n, work);
+  counts_kernel<<<1, 64, 0, s>>>(fpre + n, cpre + ngcap, nleaf, info);
+  if (!fetch(offsetof(BuildInfo, ng), sizeof(BuildInfo) - offsetof(BuildInfo, ng)))
+    return fail("group and work counts failed");
+  const int64_t ng = hinfo->ng, nw = hinfo->nw;
+  h.nc_dev = nc;
+  h.ng_dev = ng;
+  h.nw_dev = nw;
+  h.n_leaves = hinfo->leaves;
 
   dt.part = reinterpret_cast<const float*>(part);
   dt.perm = perm;
@@ -896,6 +938,7 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   out.mp64 = mp64;
   out.geo_host = reinterpret_cast<const float*>(geo_host);
   out.depth = depth;
+  out.groups = groups;
   return 0;
 }
 
