@@ -212,7 +212,7 @@ def W_sample(n, w):
 
 
 def learned_vs_theta(T, w, steps, band=None, beta=30.0, target=1e-3, params=None,
-                     band_rel=(-0.03, 0.25)):
+                     band_rel=(-0.015, 0.25)):
     """The learned acceptance criterion against the opening angle at equal
     p99 relative force error (against the GPU direct sum on the 4096-particle
     sample): theta* by bisection, then tau_pair (budget = beta * tau_pair) by
@@ -352,8 +352,8 @@ def main():
                     help="tau_pair of --mac learned (budget --beta x tau)")
     ap.add_argument("--band", type=float, nargs=2, default=None, metavar=("LO", "HI"),
                     help="opening angles bounding the learned criterion's band (--mac learned: "
-                         "default 0.4 0.8; learned-vs-theta: default theta*-0.03, theta*+0.25)")
-    ap.add_argument("--band-rel", type=float, nargs=2, default=(-0.03, 0.25), metavar=("A", "B"),
+                         "default 0.4 0.8; learned-vs-theta: default theta*-0.015, theta*+0.25)")
+    ap.add_argument("--band-rel", type=float, nargs=2, default=(-0.015, 0.25), metavar=("A", "B"),
                     help="learned-vs-theta comparison: band (theta* + A, theta* + B) unless "
                          "--band is given")
     ap.add_argument("--beta", type=float, default=30.0,

@@ -284,8 +284,8 @@ def test_learned_frontier_fallback_kernel(setup, monkeypatch):
 
 def test_learned_full_size_in_the_bench_configuration():
     """2^20 Plummer sphere with the shipped network at the operating point the
-    benchmark measures (band theta* - 0.03 .. theta* + 0.25 around theta* =
-    0.5625, tau_pair 3.79e-4, budget 30 tau_pair): the whole call's lists
+    benchmark measures (band theta* - 0.015 .. theta* + 0.25 around theta* =
+    0.5625, tau_pair 3.46e-4, budget 30 tau_pair): the whole call's lists
     replayed by the oracle bit for bit, and the forces of 300 sampled groups
     within the gates of the oracle's FP64 evaluation of those lists."""
     torch = _torch()
@@ -293,11 +293,11 @@ def test_learned_full_size_in_the_bench_configuration():
     pos, m = W.make("plummer1m")
     T = og.Tree(pos, m, 16, 64)
     O = oracle.Tree(pos, m, 16, 64)
-    tau = 3.7855e-4
-    T.set_mac(og.Mlp(L.load_params()), 0.5325, 0.8125, tau, 30 * tau)
+    tau = 3.46e-4
+    T.set_mac(og.Mlp(L.load_params()), 0.5475, 0.8125, tau, 30 * tau)
     off, cells, scores, fb = T.mac_trace(0.5625)
     g = np.repeat(np.arange(off.size - 1, dtype=np.int32), np.diff(off))
-    ref, rfb = O.lists_learned(0.5625, 0.5325, 0.8125, oracle.log10_threshold(tau),
+    ref, rfb = O.lists_learned(0.5625, 0.5475, 0.8125, oracle.log10_threshold(tau),
                                30 * tau, replay=(g, cells, scores))
     for a, b in zip(T.lists(0.5625), ref):
         assert np.array_equal(a, b)
