@@ -209,14 +209,15 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(DevTree T, const floa
                                                            const float* pot, double* part_sums) {
   __shared__ double sh[4][256];
   double p0 = 0, p1 = 0, p2 = 0, w = 0;
+  // In the caller's order: the outputs are read in sequence and only the mass
+  // is gathered (through iperm).
   const float4* part = reinterpret_cast<const float4*>(T.part);
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < T.n; i += (int64_t)gridDim.x * 256) {
-    const double m = part[i].w;
-    const int64_t o = T.perm[i];
-    p0 += m * (double)acc[3 * o];
-    p1 += m * (double)acc[3 * o + 1];
-    p2 += m * (double)acc[3 * o + 2];
-    if (pot) w += 0.5 * m * (double)pot[o];
+    const double m = part[T.iperm[i]].w;
+    p0 += m * (double)acc[3 * i];
+    p1 += m * (double)acc[3 * i + 1];
+    p2 += m * (double)acc[3 * i + 2];
+    if (pot) w += 0.5 * m * (double)pot[i];
   }
   sh[0][threadIdx.x] = p0;
   sh[1][threadIdx.x] = p1;

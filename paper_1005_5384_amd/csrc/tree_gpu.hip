@@ -57,23 +57,38 @@ __global__ void bbox_kernel(const float* __restrict__ pos, int64_t n, float* __r
   if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// Root cube from the bounding-box partials with the host's rules (block
-// partials reduced in block order keeping the earlier of equal values; the
-// cube of the largest extent rounded up to a power of two, centred on the
-// box; FP64, the same operations): cube = corner xyz, side, grid step, 1 / step.
-__global__ void root_kernel(const float* __restrict__ part, int nbb, double* __restrict__ cube) {
+// Root cube from the bounding-box partials with the host's rules (min / max
+// keeping the earlier of equal values, combined over contiguous ranges in
+// index order; the cube of the largest extent rounded up to a power of two,
+// centred on the box; FP64, the same operations): cube = corner xyz, side,
+// grid step, 1 / step.  One block of kT threads.
+__global__ __launch_bounds__(kT) void root_kernel(const float* __restrict__ part, int nbb,
+                                                  double* __restrict__ cube) {
 #pragma clang fp contract(off)
-  if (threadIdx.x != 0) return;
+  __shared__ float sh[6][kT];
+  const int t = threadIdx.x, per = (nbb + kT - 1) / kT;
+  float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int i = t * per; i < min(nbb, (t + 1) * per); ++i)
+    for (int k = 0; k < 3; ++k) {
+      const float x = part[6 * i + k], y = part[6 * i + 3 + k];
+      v[k] = x < v[k] ? x : v[k];
+      v[3 + k] = v[3 + k] < y ? y : v[3 + k];
+    }
+  for (int k = 0; k < 6; ++k) sh[k][t] = v[k];
+  __syncthreads();
+  for (int w = 1; w < kT; w <<= 1) {  // thread t holds [t, t + 2w) after this round
+    if ((t & (2 * w - 1)) == 0)
+      for (int k = 0; k < 6; ++k) {
+        const float a = sh[k][t], b = sh[k][t + w];
+        sh[k][t] = k < 3 ? (b < a ? b : a) : (a < b ? b : a);
+      }
+    __syncthreads();
+  }
+  if (t != 0) return;
   double lo[3], hi[3];
   for (int k = 0; k < 3; ++k) {
-    float a = part[k], b = part[3 + k];
-    for (int i = 1; i < nbb; ++i) {
-      const float x = part[6 * i + k], y = part[6 * i + 3 + k];
-      a = x < a ? x : a;
-      b = b < y ? y : b;
-    }
-    lo[k] = a;
-    hi[k] = b;
+    lo[k] = sh[k][0];
+    hi[k] = sh[3 + k][0];
   }
   const double e1 = hi[1] - lo[1], e2 = hi[2] - lo[2], e0 = hi[0] - lo[0];
   const double e12 = e1 < e2 ? e2 : e1;
@@ -728,7 +743,7 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   float* bbp = S.get<float>(6 * nbb);
   if (!bbp) return fail("device allocation failed");
   bbox_kernel<<<nbb, kT, 0, s>>>(pos, n, bbp);
-  root_kernel<<<1, 64, 0, s>>>(bbp, nbb, info->cube);
+  root_kernel<<<1, kT, 0, s>>>(bbp, nbb, info->cube);
 
   // Keys and the stable sort (ties keep the input order).
   uint64_t* key = S.get<uint64_t>(n);
