@@ -180,18 +180,16 @@ def integration_rate(n, theta, eps, steps, dt=1.0 / 256):
             "virial_2K_over_W": 2 * e0["K"] / abs(e0["W"])}
 
 
-def list_spread(T, theta):
+def list_spread(T, theta, eps):
     """Spread of the theta walk's per-group list lengths |C_g|, |L_g| and
-    source-particle counts n_pp(g), and of the algorithmic FLOPs per 32-target
+    source-particle counts n_pp(g) (the library's per-group counts of one
+    force call; no list export), and of the algorithmic FLOPs per 32-target
     work item (the unit a wave takes from the work counter)."""
-    c_off, c_ids, l_off, l_ids = T.lists(theta)
+    T.forces(theta, eps)
+    cnt = T.group_counts().astype(np.int64)
+    n_c, n_l, n_pp = cnt[:, 0], cnt[:, 1], cnt[:, 2]
     ex = T.export()
-    cnt = ex["topo"][:, 3].astype(np.int64)
-    gsize = cnt[ex["groups"]]
-    n_c = np.diff(c_off)
-    n_l = np.diff(l_off)
-    cs = np.concatenate([[0], np.cumsum(cnt[l_ids])])
-    n_pp = cs[l_off[1:]] - cs[l_off[:-1]]
+    gsize = ex["topo"][ex["groups"], 3].astype(np.int64)
     items = (gsize + 31) // 32
     g = np.repeat(np.arange(gsize.size), items)
     k = np.arange(g.size) - np.repeat(np.cumsum(items) - items, items)
@@ -361,8 +359,6 @@ def main():
     ap.add_argument("--params", default=None,
                     help="network parameters of the learned criterion (.npy, 5057 float32; "
                          "default: the shipped network)")
-    ap.add_argument("--list-spread", action="store_true",
-                    help="report per-group list lengths and per-work-item FLOPs (on for clumps4m)")
     ap.add_argument("--no-valu-rate", action="store_true",
                     help="skip the measurement of the non-packed VALU instruction rates")
     ap.add_argument("--no-sweep", action="store_true",
@@ -508,9 +504,9 @@ def main():
                               "theta_hi": band[1], "budget": args.beta * args.tau})
         out["mac_stats"] = T.mac_stats()
         T.set_mac(None)
-    if args.list_spread or (args.workload == "clumps4m" and args.mac == "theta"):
+    if args.mac == "theta":
         log("bench: list-length spread ...")
-        out["list_spread"] = list_spread(T, theta)
+        out["list_spread"] = list_spread(T, theta, eps)
     if not args.no_integration and args.workload == "plummer1m":
         log("bench: leapfrog science rate ...")
         out["integration"] = integration_rate(n, theta, eps, args.steps)

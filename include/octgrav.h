@@ -226,6 +226,15 @@ int octgrav_diagnostics(octgrav_tree* t, double mom[3], double* w);
  * (self pairs included, as they are evaluated). */
 int octgrav_last_counts(octgrav_tree* t, int64_t out[4]);
 
+/* Per-group list lengths of the last forces/lists call over all groups
+ * (Sec. 2.2's lists, without exporting them): out (host, n_groups x 4
+ * int32) gets, for group g in the handle's group order, |C_g|, |L_g|, the
+ * particles in L_g's leaves (n_src), and a flag word (the learned criterion:
+ * 2 x band candidates visited + 1 if the group fell back to theta; the
+ * two-pass path: 1 if the group's walk needed the global-memory queues;
+ * otherwise 0).  OCTGRAV_EINVAL before any such call. */
+int octgrav_group_counts(octgrav_tree* t, int32_t* out);
+
 /* Kernel-phase times in ms of the last OCTGRAV_TIMED forces call, measured
  * with HIP events on the handle's stream: out[0] count walk, out[1] offsets,
  * out[2] write walk, out[3] evaluation (in the default fused path: walk and

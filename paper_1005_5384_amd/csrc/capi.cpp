@@ -960,6 +960,15 @@ int octgrav_last_counts(octgrav_tree* t, int64_t out[4]) {
   return OCTGRAV_OK;
 }
 
+int octgrav_group_counts(octgrav_tree* t, int32_t* out) {
+  if (!t || !out) return fail(OCTGRAV_EINVAL, "NULL argument");
+  if (!t->counts_valid) return fail(OCTGRAV_EINVAL, "no completed forces/lists call");
+  const int64_t ng = t->h.n_groups();
+  if (ng > 0 && hipMemcpy(out, t->wb.cnt, (size_t)ng * 16, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(OCTGRAV_EHIP, "group counts copy failed");
+  return OCTGRAV_OK;
+}
+
 int octgrav_direct(octgrav_tree* t, float eps, const int32_t* targets, int64_t nt, float* acc,
                    float* pot) {
   g_err.clear();

@@ -52,7 +52,7 @@ EXPORTED = ["octgrav_build_tree", "octgrav_build_tree_ex", "octgrav_forces", "oc
             "octgrav_free", "octgrav_last_error", "octgrav_set_stream", "octgrav_tree_stats",
             "octgrav_export_tree", "octgrav_lists", "octgrav_lists_ex", "octgrav_lists_select",
             "octgrav_diagnostics",
-            "octgrav_last_counts", "octgrav_direct", "octgrav_mac_collect",
+            "octgrav_last_counts", "octgrav_group_counts", "octgrav_direct", "octgrav_mac_collect",
             "octgrav_last_timings", "octgrav_mlp_create", "octgrav_mlp_free",
             "octgrav_mlp_set_stream", "octgrav_mlp_set_params", "octgrav_mlp_get_params",
             "octgrav_mlp_get_moments", "octgrav_mlp_set_state",
@@ -97,6 +97,7 @@ def lib():
                                            C.POINTER(i64), C.POINTER(i64)]
         L.octgrav_diagnostics.argtypes = [vp, vp, vp]
         L.octgrav_last_counts.argtypes = [vp, vp]
+        L.octgrav_group_counts.argtypes = [vp, vp]
         L.octgrav_last_timings.argtypes = [vp, vp]
         L.octgrav_direct.argtypes = [vp, f32, vp, i64, vp, vp]
         L.octgrav_mac_collect.argtypes = [vp, f32, f32, f32, vp, i32, vp, vp, vp, vp, i64,
@@ -325,6 +326,13 @@ class Tree:
         out = np.zeros(4, np.int64)
         _check(lib().octgrav_last_counts(self._h, _ptr(out)))
         return dict(n_c=int(out[0]), n_l=int(out[1]), n_pc=int(out[2]), n_pp=int(out[3]))
+
+    def group_counts(self):
+        """Per-group (|C_g|, |L_g|, n_src(L_g), flags) of the last forces/lists
+        call, int32 [n_groups, 4] in the handle's group order."""
+        out = np.zeros((self.stats["n_groups"], 4), np.int32)
+        _check(lib().octgrav_group_counts(self._h, _ptr(out)))
+        return out
 
     def last_timings(self):
         out = np.zeros(6)

@@ -175,6 +175,8 @@ def test_forces_c2_sampled(c2, theta, path):
     lc = T.last_counts()
     assert lc["n_c"] == cnt[:, 0].sum() and lc["n_l"] == cnt[:, 1].sum()
     assert lc["n_pc"] == (cnt[:, 0] * gs).sum() and lc["n_pp"] == (cnt[:, 2] * gs).sum()
+    # and so do the per-group list lengths, group by group
+    assert np.array_equal(T.group_counts()[:, :3], cnt)
 
 
 def test_plain_vs_compensated(c2):
@@ -305,3 +307,13 @@ def test_bad_arguments_rejected(c1):
         with pytest.raises(og.OctgravError) as ei:
             T.forces(theta, eps, acc=acc)
         assert ei.value.code == og.EINVAL
+
+
+def test_group_counts_need_a_call():
+    pos, m = W.plummer(2048, 5)
+    T = og.Tree(pos, m, 16, 64)
+    with pytest.raises(og.OctgravError, match="no completed"):
+        T.group_counts()
+    _gpu_forces(T, 0.6, 0.01)
+    gc = T.group_counts()
+    assert gc.shape == (T.stats["n_groups"], 4) and (gc[:, 3] == 0).all()
