@@ -130,7 +130,10 @@ struct octgrav_tree : DevAlloc {
   std::unique_ptr<SeqPool> pool;
   std::unique_ptr<BuildPools> build_pools;
 
+  int64_t* tot_host = nullptr;  // page-locked copy of the totals (read after every call)
+
   ~octgrav_tree() {
+    if (tot_host) hipHostFree(tot_host);
     for (void* p : allocs) hipFree(p);
     for (hipEvent_t e : ev)
       if (e) hipEventDestroy(e);
@@ -310,6 +313,10 @@ struct octgrav_tree : DevAlloc {
     wb.l_off = (int64_t*)p;
     if ((rc = dalloc(&p, 8 * 8))) return rc;
     wb.tot = (int64_t*)p;
+    if (!tot_host && hipHostMalloc((void**)&tot_host, 8 * 8) != hipSuccess) {
+      (void)hipGetLastError();  // read_tot then copies into pageable memory
+      tot_host = nullptr;
+    }
     if ((rc = dalloc(&p, (size_t)scan_scratch_entries(ng) * 8))) return rc;
     wb.blk = (int64_t*)p;
     if ((rc = dalloc(&p, (size_t)std::max(ng, nw) * 4))) return rc;
@@ -379,9 +386,11 @@ struct octgrav_tree : DevAlloc {
   }
 
   int read_tot(int64_t* tot8) {
-    if (hipMemcpyAsync(tot8, wb.tot, 8 * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+    int64_t* dst = tot_host ? tot_host : tot8;  // page-locked when the handle has it
+    if (hipMemcpyAsync(dst, wb.tot, 8 * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
       return fail(OCTGRAV_EHIP, std::string("device error: ") + hipGetErrorString(hipGetLastError()));
+    if (dst != tot8) std::memcpy(tot8, dst, 8 * 8);
     return OCTGRAV_OK;
   }
 
