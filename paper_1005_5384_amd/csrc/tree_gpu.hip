@@ -425,8 +425,17 @@ __device__ __forceinline__ double hmin(double a, double b) { return b < a ? b : 
 __device__ __forceinline__ double hmax(double a, double b) { return a < b ? b : a; }
 
 // Boxes and FP64 moments of the cells [a, b) (one level), as the host does.
-__global__ void moments_kernel(Cells C, const float4* __restrict__ part, int64_t a, int64_t b,
-                               double* __restrict__ box, double* __restrict__ mp64) {
+// The loads of a leaf's particles (kMomChunk at a time) and of a cell's
+// children are all issued before the sums, so a cell costs a few memory
+// round trips instead of one per particle or child.  The sums keep the
+// host's order; a slot past the end repeats the last particle or child with
+// weight +0, which leaves every sum and the box unchanged bit for bit (the
+// sums start at +0 and the inputs are finite).
+constexpr int kMomChunk = 16;
+__global__ __launch_bounds__(kT) void moments_kernel(Cells C, const float4* __restrict__ part,
+                                                     int64_t a, int64_t b,
+                                                     double* __restrict__ box,
+                                                     double* __restrict__ mp64) {
 #pragma clang fp contract(off)
   const int64_t c = a + (int64_t)blockIdx.x * kT + threadIdx.x;
   if (c >= b) return;
@@ -436,60 +445,89 @@ __global__ void moments_kernel(Cells C, const float4* __restrict__ part, int64_t
   double com[3];
   if (C.nc[c] == 0) {
     const int32_t f = C.first[c], e = f + C.n[c];
-    for (int32_t i = f; i < e; ++i) {
-      const float4 p = part[i];
-      const double x[3] = {p.x, p.y, p.z};
-      for (int k = 0; k < 3; ++k) {
-        bx[k] = hmin(bx[k], x[k]);
-        bx[3 + k] = hmax(bx[3 + k], x[k]);
+    for (int32_t i0 = f; i0 < e; i0 += kMomChunk) {
+      float4 pb[kMomChunk];
+#pragma unroll
+      for (int k = 0; k < kMomChunk; ++k) pb[k] = part[i0 + k < e ? i0 + k : e - 1];
+#pragma unroll
+      for (int k = 0; k < kMomChunk; ++k) {
+        const double x[3] = {pb[k].x, pb[k].y, pb[k].z};
+        for (int d = 0; d < 3; ++d) {
+          bx[d] = hmin(bx[d], x[d]);
+          bx[3 + d] = hmax(bx[3 + d], x[d]);
+        }
+        const double w = i0 + k < e ? (double)pb[k].w : 0.0;
+        M += w;
+        sx += w * x[0];
+        sy += w * x[1];
+        sz += w * x[2];
       }
-      const double w = p.w;
-      M += w;
-      sx += w * x[0];
-      sy += w * x[1];
-      sz += w * x[2];
     }
     com[0] = sx / M;
     com[1] = sy / M;
     com[2] = sz / M;
-    for (int32_t i = f; i < e; ++i) {
-      const float4 p = part[i];
-      const double d0 = p.x - com[0], d1 = p.y - com[1], d2 = p.z - com[2], w = p.w;
-      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-      Q[0] += w * (3 * d0 * d0 - r2);
-      Q[1] += w * (3 * d1 * d1 - r2);
-      Q[2] += w * (3 * d2 * d2 - r2);
-      Q[3] += w * 3 * d0 * d1;
-      Q[4] += w * 3 * d0 * d2;
-      Q[5] += w * 3 * d1 * d2;
+    for (int32_t i0 = f; i0 < e; i0 += kMomChunk) {
+      float4 pb[kMomChunk];
+#pragma unroll
+      for (int k = 0; k < kMomChunk; ++k) pb[k] = part[i0 + k < e ? i0 + k : e - 1];
+#pragma unroll
+      for (int k = 0; k < kMomChunk; ++k) {
+        const float4 p = pb[k];
+        const double d0 = p.x - com[0], d1 = p.y - com[1], d2 = p.z - com[2];
+        const double w = i0 + k < e ? (double)p.w : 0.0;
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        Q[0] += w * (3 * d0 * d0 - r2);
+        Q[1] += w * (3 * d1 * d1 - r2);
+        Q[2] += w * (3 * d2 * d2 - r2);
+        Q[3] += w * 3 * d0 * d1;
+        Q[4] += w * 3 * d0 * d2;
+        Q[5] += w * 3 * d1 * d2;
+      }
     }
   } else {
-    const int32_t f = C.fc[c], e = f + C.nc[c];
-    for (int32_t ch = f; ch < e; ++ch) {
-      const double* cb = box + 6 * (int64_t)ch;
-      const double* cq = mp64 + 10 * (int64_t)ch;
-      for (int k = 0; k < 3; ++k) {
-        bx[k] = hmin(bx[k], cb[k]);
-        bx[3 + k] = hmax(bx[3 + k], cb[3 + k]);
+    const int32_t f = C.fc[c], nk = C.nc[c];  // 1 ... 8 children
+    double cb[8][6], cm[8][4];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t ch = f + (k < nk ? k : nk - 1);
+#pragma unroll
+      for (int d = 0; d < 6; ++d) cb[k][d] = box[6 * ch + d];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) cm[k][d] = mp64[10 * ch + d];
+      if (k >= nk) cm[k][0] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      for (int d = 0; d < 3; ++d) {
+        bx[d] = hmin(bx[d], cb[k][d]);
+        bx[3 + d] = hmax(bx[3 + d], cb[k][3 + d]);
       }
-      M += cq[0];
-      sx += cq[0] * cq[1];
-      sy += cq[0] * cq[2];
-      sz += cq[0] * cq[3];
+      M += cm[k][0];
+      sx += cm[k][0] * cm[k][1];
+      sy += cm[k][0] * cm[k][2];
+      sz += cm[k][0] * cm[k][3];
     }
     com[0] = sx / M;
     com[1] = sy / M;
     com[2] = sz / M;
-    for (int32_t ch = f; ch < e; ++ch) {
-      const double* cq = mp64 + 10 * (int64_t)ch;
-      const double d0 = cq[1] - com[0], d1 = cq[2] - com[1], d2 = cq[3] - com[2], w = cq[0];
+    double cq[8][6];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t ch = f + (k < nk ? k : nk - 1);
+#pragma unroll
+      for (int d = 0; d < 6; ++d) cq[k][d] = k < nk ? mp64[10 * ch + 4 + d] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double d0 = cm[k][1] - com[0], d1 = cm[k][2] - com[1], d2 = cm[k][3] - com[2];
+      const double w = cm[k][0];
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-      Q[0] += cq[4] + w * (3 * d0 * d0 - r2);
-      Q[1] += cq[5] + w * (3 * d1 * d1 - r2);
-      Q[2] += cq[6] + w * (3 * d2 * d2 - r2);
-      Q[3] += cq[7] + w * 3 * d0 * d1;
-      Q[4] += cq[8] + w * 3 * d0 * d2;
-      Q[5] += cq[9] + w * 3 * d1 * d2;
+      Q[0] += cq[k][0] + w * (3 * d0 * d0 - r2);
+      Q[1] += cq[k][1] + w * (3 * d1 * d1 - r2);
+      Q[2] += cq[k][2] + w * (3 * d2 * d2 - r2);
+      Q[3] += cq[k][3] + w * 3 * d0 * d1;
+      Q[4] += cq[k][4] + w * 3 * d0 * d2;
+      Q[5] += cq[k][5] + w * 3 * d1 * d2;
     }
   }
   double* o = box + 6 * c;
