@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kT) void root_kernel(const float* __restrict__ part
     }
   for (int k = 0; k < 6; ++k) sh[k][t] = v[k];
   __syncthreads();
-  for (int w = 1; w < kT; w <<= 1) {  // thread t holds [t, t + 2w) after this round
+  for (int w = 1; w < kT; w <<= 1) {  // thread t holds [t, t + 2w) after this step
     if ((t & (2 * w - 1)) == 0)
       for (int k = 0; k < 6; ++k) {
         const float a = sh[k][t], b = sh[k][t + w];
@@ -267,6 +267,27 @@ __device__ OctantLane octant_lane(const Cells& C, const uint64_t* __restrict__ k
   return o;
 }
 
+// octant_lane from the boundaries split_level_kernel stored (bnd[8 j + d] =
+// lane d's search result, the cell's first particle where nothing was
+// searched): the same result without the searches.
+__device__ OctantLane octant_lane_stored(const Cells& C, const int32_t* __restrict__ bnd,
+                                         int64_t beg, int64_t j, bool valid, int L, int n_leaf) {
+  const int d = threadIdx.x & 7;
+  OctantLane o{beg + j, 0, 0, false};
+  int32_t b = 0, l = 0;
+  bool split = false;
+  if (valid) {
+    b = C.first[o.c] + C.n[o.c];
+    split = !(C.n[o.c] <= n_leaf || L == kMaxDepth);
+    l = bnd[8 * j + d];
+  }
+  const int32_t nx = __shfl_down(l, 1, 8);
+  o.lo = l;
+  o.hi = d == 7 ? b : nx;
+  o.child = split && o.hi > o.lo;
+  return o;
+}
+
 // Non-empty children among the eight lanes of this lane's group, and how many
 // of them come before this lane.
 __device__ void octant_counts(bool child, int* n, int* before) {
@@ -324,11 +345,13 @@ __global__ void level_init_kernel(Cells C, Level* lv, int32_t n) {
 }
 
 // Children counts of level L's cells (nkid[j] for cell beg + j) and per-block
-// sums; eight lanes per cell.
+// sums; eight lanes per cell.  A level of at most bcap cells also keeps the
+// octant boundaries in bnd for emit_level_kernel.
 __global__ __launch_bounds__(kT) void split_level_kernel(Cells C, const uint64_t* __restrict__ key,
                                                          const Level* __restrict__ lv, int L,
                                                          int n_leaf, int32_t* __restrict__ nkid,
-                                                         int32_t* __restrict__ bsum) {
+                                                         int32_t* __restrict__ bsum,
+                                                         int32_t* __restrict__ bnd, int64_t bcap) {
   __shared__ int sh[kT / 64];
   const int64_t beg = lv[L].beg, m = lv[L].end - beg;
   const int64_t chunk = (m + kLB - 1) / kLB;
@@ -339,6 +362,7 @@ __global__ __launch_bounds__(kT) void split_level_kernel(Cells C, const uint64_t
     const OctantLane o = octant_lane(C, key, beg, j, j < j1, L, n_leaf);
     int k, before;
     octant_counts(o.child, &k, &before);
+    if (j < j1 && m <= bcap) bnd[8 * j + (threadIdx.x & 7)] = o.lo;
     if ((threadIdx.x & 7) == 0 && j < j1) {
       nkid[j] = k;
       s += k;
@@ -370,12 +394,15 @@ __global__ __launch_bounds__(kT) void level_scan_kernel(int32_t* __restrict__ bs
 }
 
 // Writes level L's children in cell order (the scan's numbering); eight
-// lanes per cell, one per octant.
+// lanes per cell, one per octant, with the boundaries split_level_kernel
+// kept (searched again for a level of more than bcap cells).
 __global__ __launch_bounds__(kT) void emit_level_kernel(Cells C, const uint64_t* __restrict__ key,
                                                         const Level* __restrict__ lv, int L,
                                                         int n_leaf,
                                                         const int32_t* __restrict__ nkid,
-                                                        const int32_t* __restrict__ bsum) {
+                                                        const int32_t* __restrict__ bsum,
+                                                        const int32_t* __restrict__ bnd,
+                                                        int64_t bcap) {
   __shared__ int sh[kT / 64];
   if (lv[L].overflow) return;
   const int64_t beg = lv[L].beg, end = lv[L].end, m = end - beg;
@@ -385,7 +412,8 @@ __global__ __launch_bounds__(kT) void emit_level_kernel(Cells C, const uint64_t*
   for (int64_t base = j0; base < j1; base += kT / 8) {
     const int64_t j = base + threadIdx.x / 8;
     const bool valid = j < j1;
-    const OctantLane o = octant_lane(C, key, beg, j, valid, L, n_leaf);
+    const OctantLane o = m <= bcap ? octant_lane_stored(C, bnd, beg, j, valid, L, n_leaf)
+                                   : octant_lane(C, key, beg, j, valid, L, n_leaf);
     int k, before;
     octant_counts(o.child, &k, &before);
     const bool lead = (threadIdx.x & 7) == 0;
@@ -830,6 +858,11 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
     Level* lv = info->lv;
     int32_t* nkid = S.get<int32_t>(cap);
     int32_t* bsum = S.get<int32_t>(kLB);
+    // The octant boundaries (eight per cell) go into the unsorted keys, dead
+    // after the sort: levels of up to n / 4 cells keep them, larger ones
+    // (only trees with very small leaves) are searched again.
+    int32_t* bnd = reinterpret_cast<int32_t*>(key);
+    const int64_t bcap = n / 4;
     if (!nkid || !bsum) return fail("device allocation failed");
     level_init_kernel<<<1, 64, 0, s>>>(C, lv, (int32_t)n);
     // A rebuild launches the levels its previous tree had plus two, then
@@ -840,9 +873,9 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
     if (pools && pools->last_levels > 0) L1 = std::min(kMaxDepth, pools->last_levels + 1);
     for (;;) {
       for (int L = L0; L <= L1; ++L) {
-        split_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum);
+        split_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum, bnd, bcap);
         level_scan_kernel<<<1, kT, 0, s>>>(bsum, lv, L, cap);
-        emit_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum);
+        emit_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum, bnd, bcap);
       }
       if (!fetch(0, offsetof(BuildInfo, ng))) return fail("subdivision failed");
       if (hinfo->bad & 1) return fail("positions must be finite with |x| < 2^60");
