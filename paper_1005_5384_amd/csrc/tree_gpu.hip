@@ -344,13 +344,12 @@ __global__ void level_init_kernel(Cells C, Level* lv, int32_t n) {
   }
 }
 
-// Children counts of level L's cells (nkid[j] for cell beg + j) and per-block
-// sums; eight lanes per cell.  A level of at most bcap cells also keeps the
-// octant boundaries in bnd for emit_level_kernel.
+// Children of level L's cells counted per block (bsum); eight lanes per
+// cell.  A level of at most bcap cells also keeps the octant boundaries in
+// bnd for emit_level_kernel.
 __global__ __launch_bounds__(kT) void split_level_kernel(Cells C, const uint64_t* __restrict__ key,
                                                          const Level* __restrict__ lv, int L,
-                                                         int n_leaf, int32_t* __restrict__ nkid,
-                                                         int32_t* __restrict__ bsum,
+                                                         int n_leaf, int32_t* __restrict__ bsum,
                                                          int32_t* __restrict__ bnd, int64_t bcap) {
   __shared__ int sh[kT / 64];
   const int64_t beg = lv[L].beg, m = lv[L].end - beg;
@@ -363,52 +362,40 @@ __global__ __launch_bounds__(kT) void split_level_kernel(Cells C, const uint64_t
     int k, before;
     octant_counts(o.child, &k, &before);
     if (j < j1 && m <= bcap) bnd[8 * j + (threadIdx.x & 7)] = o.lo;
-    if ((threadIdx.x & 7) == 0 && j < j1) {
-      nkid[j] = k;
-      s += k;
-    }
+    if ((threadIdx.x & 7) == 0 && j < j1) s += k;
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) bsum[blockIdx.x] = s;
 }
 
-// Exclusive scan of the block sums, the level's total, the capacity check,
-// and the next level's range (empty after an overflow).
-__global__ __launch_bounds__(kT) void level_scan_kernel(int32_t* __restrict__ bsum,
-                                                        Level* __restrict__ lv, int L,
-                                                        int64_t cap) {
-  __shared__ int sh[kT / 64];
-  static_assert(kLB == 2 * kT, "two block sums per thread");
-  const int a = bsum[2 * threadIdx.x], b = bsum[2 * threadIdx.x + 1];
-  int total = 0;
-  const int ex = block_exclusive(a + b, &total, sh);
-  bsum[2 * threadIdx.x] = ex;
-  bsum[2 * threadIdx.x + 1] = ex + a;
-  if (threadIdx.x == 0) {
-    const int64_t end = lv[L].end;
-    const int over = lv[L].overflow || end + total > cap;
-    lv[L].total = over ? 0 : total;
-    lv[L].overflow = over;
-    if (L + 1 < kMaxDepth + 2) lv[L + 1] = Level{end, over ? end : end + total, 0, over, 0};
-  }
-}
-
-// Writes level L's children in cell order (the scan's numbering); eight
-// lanes per cell, one per octant, with the boundaries split_level_kernel
-// kept (searched again for a level of more than bcap cells).
+// Writes level L's children in cell order; eight lanes per cell, one per
+// octant, with the boundaries split_level_kernel kept (searched again for a
+// level of more than bcap cells).  Every block sums the per-block children
+// counts before its own (its first child's offset) and all of them (the
+// level's total, for the capacity check); block 0 records the total and the
+// next level's range (empty after an overflow, which it flags there).
 __global__ __launch_bounds__(kT) void emit_level_kernel(Cells C, const uint64_t* __restrict__ key,
-                                                        const Level* __restrict__ lv, int L,
+                                                        Level* __restrict__ lv, int L,
                                                         int n_leaf,
-                                                        const int32_t* __restrict__ nkid,
                                                         const int32_t* __restrict__ bsum,
                                                         const int32_t* __restrict__ bnd,
-                                                        int64_t bcap) {
+                                                        int64_t bcap, int64_t cap) {
   __shared__ int sh[kT / 64];
-  if (lv[L].overflow) return;
+  static_assert(kLB == 2 * kT, "two block sums per thread");
+  const int i0 = 2 * (int)threadIdx.x, blk = (int)blockIdx.x;
+  const int s0 = bsum[i0], s1 = bsum[i0 + 1];
+  const int preceding = block_sum((i0 < blk ? s0 : 0) + (i0 + 1 < blk ? s1 : 0), sh);
+  const int total = block_sum(s0 + s1, sh);
   const int64_t beg = lv[L].beg, end = lv[L].end, m = end - beg;
+  const bool over = lv[L].overflow || end + total > cap;
+  if (blk == 0 && threadIdx.x == 0) {
+    lv[L].total = over ? 0 : total;
+    if (L + 1 < kMaxDepth + 2) lv[L + 1] = Level{end, over ? end : end + total, 0, over, 0};
+  }
+  if (over) return;
   const int64_t chunk = (m + kLB - 1) / kLB;
   const int64_t j0 = blockIdx.x * chunk, j1 = j0 + chunk < m ? j0 + chunk : m;
-  int64_t carry = bsum[blockIdx.x];
+  int64_t carry = preceding;
   for (int64_t base = j0; base < j1; base += kT / 8) {
     const int64_t j = base + threadIdx.x / 8;
     const bool valid = j < j1;
@@ -856,26 +843,24 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   // level by level, growing them.
   {
     Level* lv = info->lv;
-    int32_t* nkid = S.get<int32_t>(cap);
     int32_t* bsum = S.get<int32_t>(kLB);
     // The octant boundaries (eight per cell) go into the unsorted keys, dead
     // after the sort: levels of up to n / 4 cells keep them, larger ones
     // (only trees with very small leaves) are searched again.
     int32_t* bnd = reinterpret_cast<int32_t*>(key);
     const int64_t bcap = n / 4;
-    if (!nkid || !bsum) return fail("device allocation failed");
+    if (!bsum) return fail("device allocation failed");
     level_init_kernel<<<1, 64, 0, s>>>(C, lv, (int32_t)n);
     // A rebuild launches the levels its previous tree had plus two, then
-    // looks whether the next one is empty (an empty level still costs three
+    // looks whether the next one is empty (an empty level still costs two
     // launches); the rest follow only if the tree turned out deeper.  The
     // copy also brings the input check and the root cube.
     int L0 = 0, L1 = kMaxDepth;
     if (pools && pools->last_levels > 0) L1 = std::min(kMaxDepth, pools->last_levels + 1);
     for (;;) {
       for (int L = L0; L <= L1; ++L) {
-        split_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum, bnd, bcap);
-        level_scan_kernel<<<1, kT, 0, s>>>(bsum, lv, L, cap);
-        emit_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, nkid, bsum, bnd, bcap);
+        split_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, bsum, bnd, bcap);
+        emit_level_kernel<<<kLB, kT, 0, s>>>(C, key2, lv, L, n_leaf, bsum, bnd, bcap, cap);
       }
       if (!fetch(0, offsetof(BuildInfo, ng))) return fail("subdivision failed");
       if (hinfo->bad & 1) return fail("positions must be finite with |x| < 2^60");
