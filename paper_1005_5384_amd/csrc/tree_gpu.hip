@@ -441,19 +441,16 @@ __device__ __forceinline__ double hmax(double a, double b) { return a < b ? b : 
 
 // Boxes and FP64 moments of the cells [a, b) (one level), as the host does.
 // The loads of a leaf's particles (kMomChunk at a time) and of a cell's
-// children are all issued before the sums, so a cell costs a few memory
-// round trips instead of one per particle or child.  The sums keep the
+// children (four at a time) are issued before their sums, so a cell costs a
+// few memory round trips instead of one per particle or child.  The sums keep the
 // host's order; a slot past the end repeats the last particle or child with
 // weight +0, which leaves every sum and the box unchanged bit for bit (the
 // sums start at +0 and the inputs are finite).
-constexpr int kMomChunk = 16;
-__global__ __launch_bounds__(kT) void moments_kernel(Cells C, const float4* __restrict__ part,
-                                                     int64_t a, int64_t b,
-                                                     double* __restrict__ box,
-                                                     double* __restrict__ mp64) {
+constexpr int kMomChunk = 8;
+__device__ __forceinline__ void cell_moments(const Cells& C, const float4* __restrict__ part,
+                                             int64_t c, double* __restrict__ box,
+                                             double* __restrict__ mp64) {
 #pragma clang fp contract(off)
-  const int64_t c = a + (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (c >= b) return;
   double bx[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
   double M = 0, sx = 0, sy = 0, sz = 0;
   double Q[6] = {0, 0, 0, 0, 0, 0};
@@ -500,49 +497,60 @@ __global__ __launch_bounds__(kT) void moments_kernel(Cells C, const float4* __re
       }
     }
   } else {
+    // Children in two batches of four (a batch's loads first, then its sums
+    // in child order), which keeps the kernel at a few waves per SIMD.
     const int32_t f = C.fc[c], nk = C.nc[c];  // 1 ... 8 children
-    double cb[8][6], cm[8][4];
+#pragma unroll 1
+    for (int h = 0; h < nk; h += 4) {
+      double cb[4][6], cm[4][4];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int64_t ch = f + (k < nk ? k : nk - 1);
+      for (int k = 0; k < 4; ++k) {
+        const int64_t ch = f + (h + k < nk ? h + k : nk - 1);
 #pragma unroll
-      for (int d = 0; d < 6; ++d) cb[k][d] = box[6 * ch + d];
+        for (int d = 0; d < 6; ++d) cb[k][d] = box[6 * ch + d];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) cm[k][d] = mp64[10 * ch + d];
-      if (k >= nk) cm[k][0] = 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      for (int d = 0; d < 3; ++d) {
-        bx[d] = hmin(bx[d], cb[k][d]);
-        bx[3 + d] = hmax(bx[3 + d], cb[k][3 + d]);
+        for (int d = 0; d < 4; ++d) cm[k][d] = mp64[10 * ch + d];
+        if (h + k >= nk) cm[k][0] = 0.0;
       }
-      M += cm[k][0];
-      sx += cm[k][0] * cm[k][1];
-      sy += cm[k][0] * cm[k][2];
-      sz += cm[k][0] * cm[k][3];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        for (int d = 0; d < 3; ++d) {
+          bx[d] = hmin(bx[d], cb[k][d]);
+          bx[3 + d] = hmax(bx[3 + d], cb[k][3 + d]);
+        }
+        M += cm[k][0];
+        sx += cm[k][0] * cm[k][1];
+        sy += cm[k][0] * cm[k][2];
+        sz += cm[k][0] * cm[k][3];
+      }
     }
     com[0] = sx / M;
     com[1] = sy / M;
     com[2] = sz / M;
-    double cq[8][6];
+#pragma unroll 1
+    for (int h = 0; h < nk; h += 4) {
+      double cq[4][10];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int64_t ch = f + (k < nk ? k : nk - 1);
+      for (int k = 0; k < 4; ++k) {
+        const int64_t ch = f + (h + k < nk ? h + k : nk - 1);
 #pragma unroll
-      for (int d = 0; d < 6; ++d) cq[k][d] = k < nk ? mp64[10 * ch + 4 + d] : 0.0;
-    }
+        for (int d = 0; d < 10; ++d) cq[k][d] = mp64[10 * ch + d];
+        if (h + k >= nk)
+          for (int d = 0; d < 10; ++d) cq[k][d] = d == 0 ? 0.0 : (d < 4 ? com[d - 1] : 0.0);
+      }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const double d0 = cm[k][1] - com[0], d1 = cm[k][2] - com[1], d2 = cm[k][3] - com[2];
-      const double w = cm[k][0];
-      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-      Q[0] += cq[k][0] + w * (3 * d0 * d0 - r2);
-      Q[1] += cq[k][1] + w * (3 * d1 * d1 - r2);
-      Q[2] += cq[k][2] + w * (3 * d2 * d2 - r2);
-      Q[3] += cq[k][3] + w * 3 * d0 * d1;
-      Q[4] += cq[k][4] + w * 3 * d0 * d2;
-      Q[5] += cq[k][5] + w * 3 * d1 * d2;
+      for (int k = 0; k < 4; ++k) {
+        const double* q = cq[k];
+        const double d0 = q[1] - com[0], d1 = q[2] - com[1], d2 = q[3] - com[2];
+        const double w = q[0];
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        Q[0] += q[4] + w * (3 * d0 * d0 - r2);
+        Q[1] += q[5] + w * (3 * d1 * d1 - r2);
+        Q[2] += q[6] + w * (3 * d2 * d2 - r2);
+        Q[3] += q[7] + w * 3 * d0 * d1;
+        Q[4] += q[8] + w * 3 * d0 * d2;
+        Q[5] += q[9] + w * 3 * d1 * d2;
+      }
     }
   }
   double* o = box + 6 * c;
@@ -552,6 +560,16 @@ __global__ __launch_bounds__(kT) void moments_kernel(Cells C, const float4* __re
   for (int k = 0; k < 3; ++k) q[1 + k] = com[k];
   for (int k = 0; k < 6; ++k) q[4 + k] = Q[k];
 }
+
+// Cells [a, b) of one level, one thread each.
+__global__ __launch_bounds__(kT) void moments_kernel(Cells C, const float4* __restrict__ part,
+                                                     int64_t a, int64_t b,
+                                                     double* __restrict__ box,
+                                                     double* __restrict__ mp64) {
+  const int64_t c = a + (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (c < b) cell_moments(C, part, c, box, mp64);
+}
+
 
 // FP32 images of every cell: topology, boundary (centre of the tight box,
 // side = largest extent; the device copy carries the leaf flag in the side's
