@@ -579,15 +579,17 @@ __global__ void images_kernel(Cells C, int64_t nc, const double* __restrict__ bo
                               const double* __restrict__ mp64, int4* __restrict__ topo,
                               float4* __restrict__ geo_host, float4* __restrict__ geo,
                               float4* __restrict__ wrec, float4* __restrict__ mp,
-                              float4* __restrict__ fcell, int32_t* __restrict__ n_leaves) {
+                              float4* __restrict__ fcell, int32_t* __restrict__ leaf_part) {
 #pragma clang fp contract(off)
+  __shared__ int sh[kT / 64];
   const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
+  // the block's leaf count (one store per block: same-address atomics
+  // from every wave serialise)
+  const int nl = block_sum(c < nc && C.nc[c < nc ? c : 0] == 0 ? 1 : 0, sh);
+  if (threadIdx.x == 0) leaf_part[blockIdx.x] = nl;
   if (c >= nc) return;
   const int4 tp = make_int4(C.fc[c], C.nc[c], C.first[c], C.n[c]);
   topo[c] = tp;
-  const unsigned long long leafs = __ballot(tp.y == 0);
-  if (leafs && __lane_id() == __ffsll((unsigned long long)leafs) - 1)
-    atomicAdd(n_leaves, (int32_t)__popcll(leafs));
   const double* bx = box + 6 * c;
   double l = 0;
   float g[3];
@@ -673,12 +675,20 @@ struct BuildInfo {
   int32_t ng, nw, leaves;
 };
 
-__global__ void counts_kernel(const int32_t* __restrict__ ngp, const int32_t* __restrict__ nwp,
-                              const int32_t* __restrict__ nleaf, BuildInfo* __restrict__ info) {
+// The group and work-item counts and the leaf count (sum of the images
+// kernel's nb per-block counts).
+__global__ __launch_bounds__(kT) void counts_kernel(const int32_t* __restrict__ ngp,
+                                                    const int32_t* __restrict__ nwp,
+                                                    const int32_t* __restrict__ leaf_part,
+                                                    int64_t nb, BuildInfo* __restrict__ info) {
+  __shared__ int sh[kT / 64];
+  int t = 0;
+  for (int64_t i = threadIdx.x; i < nb; i += kT) t += leaf_part[i];
+  t = block_sum(t, sh);
   if (threadIdx.x == 0) {
     info->ng = *ngp;
     info->nw = *nwp;
-    info->leaves = *nleaf;
+    info->leaves = t;
   }
 }
 
@@ -964,9 +974,9 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
       !A((void**)&mp, (size_t)nc * 48) || !A((void**)&fcell, (size_t)nc * 32) ||
       !A((void**)&depth, (size_t)nc * 4))
     return fail("device allocation failed");
-  int32_t* nleaf = S.get<int32_t>(1);
+  const int64_t nbi = blocks(nc);
+  int32_t* nleaf = S.get<int32_t>(nbi);
   if (!nleaf) return fail("device allocation failed");
-  if (hipMemsetAsync(nleaf, 0, 4, s) != hipSuccess) return fail("memset failed");
   images_kernel<<<blocks(nc), kT, 0, s>>>(C, nc, box, mp64, topo, geo_host, geo, wrec, mp, fcell,
                                           nleaf);
   if (hipMemcpyAsync(depth, C.depth, (size_t)nc * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -999,7 +1009,7 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   group_fill_kernel<<<blocks(n), kT, 0, s>>>(at, f, fpre, n, C, box, groups, ginfo, gbox, nchunk);
   if (exclusive_sum(nchunk, cpre, ngcap + 1, S, s)) return fail("scan failed");
   work_kernel<<<blocks(ngcap), kT, 0, s>>>(nchunk, cpre, fpre + n, work);
-  counts_kernel<<<1, 64, 0, s>>>(fpre + n, cpre + ngcap, nleaf, info);
+  counts_kernel<<<1, kT, 0, s>>>(fpre + n, cpre + ngcap, nleaf, nbi, info);
   if (!fetch(offsetof(BuildInfo, ng), sizeof(BuildInfo) - offsetof(BuildInfo, ng)))
     return fail("group and work counts failed");
   const int64_t ng = hinfo->ng, nw = hinfo->nw;
