@@ -356,6 +356,47 @@ __global__ __launch_bounds__(kT) void split_level_kernel(Cells C, const uint64_t
   const int64_t chunk = (m + kLB - 1) / kLB;
   const int64_t j0 = blockIdx.x * chunk, j1 = j0 + chunk < m ? j0 + chunk : m;
   int s = 0;
+  if (m <= kLB * (kT / 64) && m <= bcap) {
+    // A level of few (large) cells: a wave per cell, lanes 8 d ... 8 d + 7
+    // find boundary d by a 9-ary search (eight probes per step), about
+    // log9 instead of log2 dependent loads.
+    const int lane = threadIdx.x & 63, d = lane >> 3, r = lane & 7;
+    const int sh3 = 3 * (kMaxDepth - 1 - L);
+    for (int64_t base = j0; base < j1; base += kT / 64) {
+      const int64_t j = base + threadIdx.x / 64;  // uniform per wave
+      if (j >= j1) break;
+      const int64_t c = beg + j;
+      const int32_t a = C.first[c], b = a + C.n[c];
+      const bool split = !(C.n[c] <= n_leaf || L == kMaxDepth);
+      int32_t l = a, h = split && d > 0 ? b : a;
+      // every lane of a group of eight holds the same l, h
+      while (__any(l < h)) {
+        const int32_t w = h - l;
+        const int32_t pr = w >= 9 ? l + (int32_t)(((int64_t)w * (r + 1)) / 9) : l + r;
+        const bool live = l < h && pr < h;
+        const bool lt = live && (int)((key[pr] >> sh3) & 7) < d;
+        const uint32_t grp = (uint32_t)(__ballot(lt) >> (lane & ~7)) & 0xffu;
+        const uint32_t fal = (uint32_t)(__ballot(live && !lt) >> (lane & ~7)) & 0xffu;
+        const int nt = __popc(grp);  // probes below d (a prefix of the group)
+        const int32_t plast = __shfl(pr, (lane & ~7) + (nt > 0 ? nt - 1 : 0));
+        const int32_t pfirst = __shfl(pr, (lane & ~7) + (nt < 8 ? nt : 7));
+        if (l < h) {
+          if (nt > 0) l = plast + 1;
+          if (fal != 0) h = pfirst;
+          else if (nt == 0) h = l;  // no live probe: nothing left
+        }
+      }
+      const int32_t nx = __shfl_down(l, 8);
+      const int32_t hi = d == 7 ? b : nx;
+      const bool child = split && hi > l && r == 0;
+      const int k = __popcll(__ballot(child));
+      if (r == 0) bnd[8 * j + d] = l;
+      s += lane == 0 ? k : 0;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+    return;
+  }
   for (int64_t base = j0; base < j1; base += kT / 8) {
     const int64_t j = base + threadIdx.x / 8;
     const OctantLane o = octant_lane(C, key, beg, j, j < j1, L, n_leaf);
