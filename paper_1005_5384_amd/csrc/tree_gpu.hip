@@ -487,7 +487,10 @@ __device__ __forceinline__ double hmax(double a, double b) { return a < b ? b : 
 // host's order; a slot past the end repeats the last particle or child with
 // weight +0, which leaves every sum and the box unchanged bit for bit (the
 // sums start at +0 and the inputs are finite).
-constexpr int kMomChunk = 8;
+constexpr int kMomChunk = 16;
+// LEAVES: cell c if it is a leaf, else nothing; otherwise cell c if it has
+// children (whose moments are done), else nothing.
+template <bool LEAVES>
 __device__ __forceinline__ void cell_moments(const Cells& C, const float4* __restrict__ part,
                                              int64_t c, double* __restrict__ box,
                                              double* __restrict__ mp64) {
@@ -496,7 +499,9 @@ __device__ __forceinline__ void cell_moments(const Cells& C, const float4* __res
   double M = 0, sx = 0, sy = 0, sz = 0;
   double Q[6] = {0, 0, 0, 0, 0, 0};
   double com[3];
-  if (C.nc[c] == 0) {
+  const bool leaf = C.nc[c] == 0;
+  if (leaf != LEAVES) return;
+  if (LEAVES) {
     const int32_t f = C.first[c], e = f + C.n[c];
     for (int32_t i0 = f; i0 < e; i0 += kMomChunk) {
       float4 pb[kMomChunk];
@@ -602,13 +607,16 @@ __device__ __forceinline__ void cell_moments(const Cells& C, const float4* __res
   for (int k = 0; k < 6; ++k) q[4 + k] = Q[k];
 }
 
-// Cells [a, b) of one level, one thread each.
+// The leaves among cells [a, b) (all cells: leaves need only their
+// particles), or the cells with children among [a, b) (one level, after the
+// levels below), one thread per cell.
+template <bool LEAVES>
 __global__ __launch_bounds__(kT) void moments_kernel(Cells C, const float4* __restrict__ part,
                                                      int64_t a, int64_t b,
                                                      double* __restrict__ box,
                                                      double* __restrict__ mp64) {
   const int64_t c = a + (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (c < b) cell_moments(C, part, c, box, mp64);
+  if (c < b) cell_moments<LEAVES>(C, part, c, box, mp64);
 }
 
 
@@ -1003,9 +1011,10 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   double* mp64 = nullptr;
   if (!A((void**)&box, (size_t)nc * 48) || !A((void**)&mp64, (size_t)nc * 80))
     return fail("device allocation failed");
-  for (int L = h.max_depth; L >= 0; --L) {
+  moments_kernel<true><<<blocks(nc), kT, 0, s>>>(C, part, 0, nc, box, mp64);
+  for (int L = h.max_depth - 1; L >= 0; --L) {  // the deepest level holds only leaves
     const int64_t a = level_beg[L], b = level_beg[L + 1];
-    if (b > a) moments_kernel<<<blocks(b - a), kT, 0, s>>>(C, part, a, b, box, mp64);
+    if (b > a) moments_kernel<false><<<blocks(b - a), kT, 0, s>>>(C, part, a, b, box, mp64);
   }
   int4* topo = nullptr;
   float4 *geo_host = nullptr, *geo = nullptr, *wrec = nullptr, *mp = nullptr, *fcell = nullptr;
