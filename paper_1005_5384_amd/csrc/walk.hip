@@ -205,37 +205,55 @@ __device__ void block_max_counts(const WalkBufs& B, int64_t a, int64_t b) {
 
 // Interaction totals of the groups [g0, g0 + ng) from their counts: tot[0..3]
 // = cell entries, leaf entries, N_pc, N_pp; tot[6..7] = longest lists;
-// tot[4] set if a list outgrew its slot (slot_c > 0).  One atomic per block.
+// tot[4] set if a list outgrew its slot (slot_c > 0).  kTotBlock groups per
+// block (a few per thread, so the loads of a thread are few), one pass over
+// the counts, one atomic per total and block (integer sums and maxima: the
+// result does not depend on the order).
+constexpr int kTotBlock = 4 * kScanThreads;
 __global__ __launch_bounds__(kScanThreads) void totals_kernel(DevTree T, WalkBufs B, int64_t g0,
                                                               int64_t ng) {
-  __shared__ int64_t sh[4][kScanThreads];
-  __shared__ int over;
-  if (threadIdx.x == 0) over = 0;
-  const int64_t a = g0 + (int64_t)blockIdx.x * kScanBlock, b = min(a + kScanBlock, g0 + ng);
-  int64_t v[4] = {0, 0, 0, 0};
+  __shared__ int64_t sh[6][kScanThreads];
+  const int64_t a = g0 + (int64_t)blockIdx.x * kTotBlock, b = min(a + kTotBlock, g0 + ng);
+  int64_t v[6] = {0, 0, 0, 0, 0, 0};  // sums of 4, maxima of 2
   int ov = 0;
-  for (int64_t g = a + threadIdx.x; g < b; g += kScanThreads) {
-    const int4 c = reinterpret_cast<const int4*>(B.cnt)[g];
-    const int64_t sz = T.ginfo[4 * g + 1];
+  constexpr int kIt = kTotBlock / kScanThreads;
+  int4 cs[kIt];
+  int64_t szs[kIt];
+#pragma unroll
+  for (int it = 0; it < kIt; ++it) {  // every load first (b > a: a clamped index is a group)
+    const int64_t g = min(a + threadIdx.x + (int64_t)it * kScanThreads, b - 1);
+    cs[it] = reinterpret_cast<const int4*>(B.cnt)[g];
+    szs[it] = T.ginfo[4 * g + 1];
+  }
+#pragma unroll
+  for (int it = 0; it < kIt; ++it) {
+    if (a + threadIdx.x + (int64_t)it * kScanThreads >= b) continue;
+    const int4 c = cs[it];
+    const int64_t sz = szs[it];
     v[0] += c.x;
     v[1] += c.y;
     v[2] += sz * c.x;
     v[3] += sz * c.z;
+    v[4] = max(v[4], (int64_t)c.x);
+    v[5] = max(v[5], (int64_t)c.y);
     ov |= B.slot_c > 0 && (c.x > B.slot_c || c.y > B.slot_l);
   }
-  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = v[k];
-  __syncthreads();
-  if (ov) over = 1;
+  for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = v[k];
+  const int any_ov = __syncthreads_or(ov);
   for (int o = kScanThreads / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o)
+    if (threadIdx.x < o) {
       for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
+      for (int k = 4; k < 6; ++k) sh[k][threadIdx.x] = max(sh[k][threadIdx.x], sh[k][threadIdx.x + o]);
+    }
     __syncthreads();
   }
   if (threadIdx.x < 4)
     atomicAdd(reinterpret_cast<unsigned long long*>(&B.tot[threadIdx.x]),
               (unsigned long long)sh[threadIdx.x][0]);
-  if (threadIdx.x == 0 && over) atomicOr(reinterpret_cast<unsigned long long*>(&B.tot[4]), 1ull);
-  block_max_counts(B, a, b);
+  if (threadIdx.x == 4 || threadIdx.x == 5)
+    atomicMax(reinterpret_cast<unsigned long long*>(&B.tot[threadIdx.x + 2]),
+              (unsigned long long)sh[threadIdx.x][0]);
+  if (threadIdx.x == 0 && any_ov) atomicOr(reinterpret_cast<unsigned long long*>(&B.tot[4]), 1ull);
 }
 
 // Offsets of the groups [g0, g0 + ng): per-block sums, then per-block prefix
@@ -369,7 +387,7 @@ int launch_scan(const DevTree& T, const WalkBufs& B, void* stream, int64_t g0, i
 int launch_totals(const DevTree& T, const WalkBufs& B, void* stream, int64_t g0, int64_t ng) {
   hipStream_t s = (hipStream_t)stream;
   if (ng < 0) ng = T.ng - g0;
-  const int nb = (int)((ng + kScanBlock - 1) / kScanBlock);
+  const int nb = (int)((ng + kTotBlock - 1) / kTotBlock);
   if (nb == 0) return 0;
   totals_kernel<<<nb, kScanThreads, 0, s>>>(T, B, g0, ng);
   return hipGetLastError() == hipSuccess ? 0 : -1;
