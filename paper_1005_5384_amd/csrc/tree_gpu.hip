@@ -140,18 +140,23 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
   return x;
 }
 
-// cube: corner xyz, side, grid step, 1 / step (root_kernel).
-__global__ void keys_kernel(const float* __restrict__ pos, int64_t n,
-                            const double* __restrict__ cube, uint64_t* __restrict__ key,
-                            int32_t* __restrict__ idx) {
+// cube: corner xyz, side, grid step, 1 / step (root_kernel).  Also packs
+// each particle as (x, y, z, m) in input order, so that the gather after the
+// sort reads one aligned 16-byte record per particle.
+__global__ void keys_kernel(const float* __restrict__ pos, const float* __restrict__ mass,
+                            int64_t n, const double* __restrict__ cube,
+                            uint64_t* __restrict__ key, int32_t* __restrict__ idx,
+                            float4* __restrict__ packed) {
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (i >= n) return;
   const double step = cube[4], inv = cube[5];
-  const uint32_t u0 = grid_coord((double)pos[3 * i], cube[0], step, inv);
-  const uint32_t u1 = grid_coord((double)pos[3 * i + 1], cube[1], step, inv);
-  const uint32_t u2 = grid_coord((double)pos[3 * i + 2], cube[2], step, inv);
+  const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+  const uint32_t u0 = grid_coord((double)x, cube[0], step, inv);
+  const uint32_t u1 = grid_coord((double)y, cube[1], step, inv);
+  const uint32_t u2 = grid_coord((double)z, cube[2], step, inv);
   key[i] = spread3(u0) | spread3(u1) << 1 | spread3(u2) << 2;
   idx[i] = (int32_t)i;
+  packed[i] = make_float4(x, y, z, mass[i]);
 }
 
 struct Cells {
@@ -466,13 +471,12 @@ __global__ __launch_bounds__(kT) void emit_level_kernel(Cells C, const uint64_t*
   }
 }
 
-__global__ void gather_kernel(const float* __restrict__ pos, const float* __restrict__ mass,
-                              const int32_t* __restrict__ perm, int64_t n,
-                              float4* __restrict__ part, int32_t* __restrict__ iperm) {
+__global__ void gather_kernel(const float4* __restrict__ packed, const int32_t* __restrict__ perm,
+                              int64_t n, float4* __restrict__ part, int32_t* __restrict__ iperm) {
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (i >= n) return;
   const int32_t p = perm[i];
-  part[i] = make_float4(pos[3 * p], pos[3 * p + 1], pos[3 * p + 2], mass[p]);
+  part[i] = packed[p];
   iperm[p] = (int32_t)i;
 }
 
@@ -881,7 +885,9 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   int32_t* idx = S.get<int32_t>(n);
   int32_t* perm = nullptr;
   if (!key || !key2 || !idx || alloc.alloc((void**)&perm, (size_t)n * 4)) return fail("device allocation failed");
-  keys_kernel<<<blocks(n), kT, 0, s>>>(pos, n, info->cube, key, idx);
+  float4* packed = S.get<float4>(n);
+  if (!packed) return fail("device allocation failed");
+  keys_kernel<<<blocks(n), kT, 0, s>>>(pos, mass, n, info->cube, key, idx, packed);
   size_t sbytes = 0;
   if (hipcub::DeviceRadixSort::SortPairs(nullptr, sbytes, key, key2, idx, perm, (int)n, 0, 63, s) !=
       hipSuccess)
@@ -1005,7 +1011,7 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   int32_t* iperm = nullptr;
   if (!A((void**)&part, (size_t)n * 16) || !A((void**)&iperm, (size_t)n * 4))
     return fail("device allocation failed");
-  gather_kernel<<<blocks(n), kT, 0, s>>>(pos, mass, perm, n, part, iperm);
+  gather_kernel<<<blocks(n), kT, 0, s>>>(packed, perm, n, part, iperm);
 
   double* box = nullptr;
   double* mp64 = nullptr;
