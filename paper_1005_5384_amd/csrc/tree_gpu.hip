@@ -626,13 +626,14 @@ __global__ __launch_bounds__(kT) void moments_kernel(Cells C, const float4* __re
 
 // FP32 images of every cell: topology, boundary (centre of the tight box,
 // side = largest extent; the device copy carries the leaf flag in the side's
-// sign bit), walk record, moments, and the learned criterion's cell features
+// sign bit), walk record, moments, depth, and the learned criterion's cell features
 // with the host's FP32 expressions.
 __global__ void images_kernel(Cells C, int64_t nc, const double* __restrict__ box,
                               const double* __restrict__ mp64, int4* __restrict__ topo,
                               float4* __restrict__ geo_host, float4* __restrict__ geo,
                               float4* __restrict__ wrec, float4* __restrict__ mp,
-                              float4* __restrict__ fcell, int32_t* __restrict__ leaf_part) {
+                              float4* __restrict__ fcell, int32_t* __restrict__ depth,
+                              int32_t* __restrict__ leaf_part) {
 #pragma clang fp contract(off)
   __shared__ int sh[kT / 64];
   const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
@@ -643,6 +644,8 @@ __global__ void images_kernel(Cells C, int64_t nc, const double* __restrict__ bo
   if (c >= nc) return;
   const int4 tp = make_int4(C.fc[c], C.nc[c], C.first[c], C.n[c]);
   topo[c] = tp;
+  const int32_t dc = C.depth[c];
+  depth[c] = dc;
   const double* bx = box + 6 * c;
   double l = 0;
   float g[3];
@@ -675,7 +678,7 @@ __global__ void images_kernel(Cells C, int64_t nc, const double* __restrict__ bo
   fcell[2 * c] = make_float4(log10f(M / mtot) / 3.0f, qn / (M * lf * lf),
                              (float)(bx[3] - bx[0]) / lf, (float)(bx[4] - bx[1]) / lf);
   fcell[2 * c + 1] = make_float4((float)(bx[5] - bx[2]) / lf,
-                                 log2f(1.0f + (float)C.depth[c]) / log2f(22.0f), sqrtf(s2) / lf,
+                                 log2f(1.0f + (float)dc) / log2f(22.0f), sqrtf(s2) / lf,
                                  0.0f);
 }
 
@@ -1034,9 +1037,7 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   int32_t* nleaf = S.get<int32_t>(nbi);
   if (!nleaf) return fail("device allocation failed");
   images_kernel<<<blocks(nc), kT, 0, s>>>(C, nc, box, mp64, topo, geo_host, geo, wrec, mp, fcell,
-                                          nleaf);
-  if (hipMemcpyAsync(depth, C.depth, (size_t)nc * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return fail("copy failed");
+                                          depth, nleaf);
 
   // Groups and work chunks, sized by bounds known here (groups <= cells,
   // work items <= groups + n / kChunk), so that their counts come back in
