@@ -685,17 +685,24 @@ __global__ void images_kernel(Cells C, int64_t nc, const double* __restrict__ bo
 // Groups: the maximal cells with at most n_group particles, or leaves; their
 // particle ranges partition the particles, so marking each group at its first
 // particle and compacting orders them by first particle.
-__global__ void group_mark_kernel(Cells C, int64_t nc, int n_group, int32_t* __restrict__ at) {
+// (Also clears the nc + 1 per-group chunk counts that group_fill_kernel
+// fills and the chunk scan reads.)
+__global__ void group_mark_kernel(Cells C, int64_t nc, int n_group, int32_t* __restrict__ at,
+                                  int32_t* __restrict__ nchunk) {
   const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (c >= nc) return;
+  if (c > nc) return;
+  nchunk[c] = 0;
+  if (c == nc) return;
   const bool cand = C.n[c] <= n_group || C.nc[c] == 0;
   const bool top = c == 0 || C.n[C.parent[c]] > n_group;
   if (cand && top) at[C.first[c]] = (int32_t)c;
 }
 
+// Group-start flags of the n particles, and a 0 at f[n] for the scan.
 __global__ void flag_kernel(const int32_t* __restrict__ at, int64_t n, int32_t* __restrict__ f) {
   const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (i < n) f[i] = at[i] >= 0;
+  else if (i == n) f[n] = 0;
 }
 
 __global__ void group_fill_kernel(const int32_t* __restrict__ at, const int32_t* __restrict__ f,
@@ -1046,11 +1053,12 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   int32_t* at = S.get<int32_t>(n);
   int32_t* f = S.get<int32_t>(n + 1);
   int32_t* fpre = S.get<int32_t>(n + 1);
-  if (!at || !f || !fpre) return fail("device allocation failed");
+  int32_t* nchunk = S.get<int32_t>(ngcap + 1);
+  int32_t* cpre = S.get<int32_t>(ngcap + 1);
+  if (!at || !f || !fpre || !nchunk || !cpre) return fail("device allocation failed");
   if (hipMemsetAsync(at, 0xff, (size_t)n * 4, s) != hipSuccess) return fail("memset failed");
-  group_mark_kernel<<<blocks(nc), kT, 0, s>>>(C, nc, n_group, at);
-  flag_kernel<<<blocks(n), kT, 0, s>>>(at, n, f);
-  if (hipMemsetAsync(f + n, 0, 4, s) != hipSuccess) return fail("memset failed");
+  group_mark_kernel<<<blocks(nc + 1), kT, 0, s>>>(C, nc, n_group, at, nchunk);
+  flag_kernel<<<blocks(n + 1), kT, 0, s>>>(at, n, f);
   if (exclusive_sum(f, fpre, n + 1, S, s)) return fail("scan failed");
   int32_t* groups = nullptr;
   int4* ginfo = nullptr;
@@ -1059,10 +1067,6 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
   if (!A((void**)&groups, (size_t)ngcap * 4) || !A((void**)&ginfo, (size_t)ngcap * 16) ||
       !A((void**)&gbox, (size_t)ngcap * 32) || !A((void**)&work, (size_t)nwcap * 8))
     return fail("device allocation failed");
-  int32_t* nchunk = S.get<int32_t>(ngcap + 1);
-  int32_t* cpre = S.get<int32_t>(ngcap + 1);
-  if (!nchunk || !cpre) return fail("device allocation failed");
-  if (hipMemsetAsync(nchunk, 0, (size_t)(ngcap + 1) * 4, s) != hipSuccess) return fail("memset failed");
   group_fill_kernel<<<blocks(n), kT, 0, s>>>(at, f, fpre, n, C, box, groups, ginfo, gbox, nchunk);
   if (exclusive_sum(nchunk, cpre, ngcap + 1, S, s)) return fail("scan failed");
   work_kernel<<<blocks(ngcap), kT, 0, s>>>(nchunk, cpre, fpre + n, work);
