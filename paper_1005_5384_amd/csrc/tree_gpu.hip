@@ -33,17 +33,32 @@ inline int blocks(int64_t n) { return (int)((n + kT - 1) / kT); }
 
 // Bounding box: per-block min / max of each coordinate (FP32 values are
 // exact in FP64, so the order of the reduction does not matter).
-__global__ void bbox_kernel(const float* __restrict__ pos, int64_t n, float* __restrict__ part) {
+// With mass != nullptr (inputs already on the device) it also checks them in
+// the same pass: bit 1 of *bad = a position not finite or |x| >= 2^60, bit 2
+// = a mass not finite or not > 0.
+__global__ void bbox_kernel(const float* __restrict__ pos, const float* __restrict__ mass,
+                            int64_t n, float* __restrict__ part, int32_t* __restrict__ bad) {
   __shared__ float sh[6][kT];
   // min / max with the host's tie rule (keeps the earlier of equal values,
   // so +0 / -0 resolve as they do on the host)
   float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+  int bd = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     for (int k = 0; k < 3; ++k) {
       const float x = pos[3 * i + k];
       v[k] = x < v[k] ? x : v[k];
       v[3 + k] = v[3 + k] < x ? x : v[3 + k];
+      if (!(fabsf(x) < 0x1p60f)) bd |= 1;  // also catches NaN
     }
+    if (mass) {
+      const float m = mass[i];
+      if (!(m > 0.0f) || !(m < INFINITY)) bd |= 2;
+    }
+  }
+  if (mass) {
+    if (__any(bd & 1) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+    if (__any(bd & 2) && (threadIdx.x & 63) == 0) atomicOr(bad, 2);
+  }
   for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = v[k];
   __syncthreads();
   for (int o = kT / 2; o > 0; o >>= 1) {
@@ -100,23 +115,6 @@ __global__ __launch_bounds__(kT) void root_kernel(const float* __restrict__ part
   cube[3] = side;
   cube[4] = ldexp(side, -kMaxDepth);
   cube[5] = ldexp(1.0 / side, kMaxDepth);
-}
-
-// Input check of device-resident inputs: bit 1 = a position not finite or
-// |x| >= 2^60, bit 2 = a mass not finite or not > 0.
-__global__ void validate_kernel(const float* __restrict__ pos, const float* __restrict__ mass,
-                                int64_t n, int32_t* __restrict__ bad) {
-  int b = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-    for (int k = 0; k < 3; ++k) {
-      const float v = pos[3 * i + k];
-      if (!(fabsf(v) < 0x1p60f)) b |= 1;  // also catches NaN
-    }
-    const float m = mass[i];
-    if (!(m > 0.0f) || !(m < INFINITY)) b |= 2;
-  }
-  if (__any(b & 1) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
-  if (__any(b & 2) && (threadIdx.x & 63) == 0) atomicOr(bad, 2);
 }
 
 // The host's grid coordinate: floor, then exact against the grid planes.
@@ -734,7 +732,7 @@ __global__ void work_kernel(const int32_t* __restrict__ nchunk, const int32_t* _
 struct BuildInfo {
   Level lv[kMaxDepth + 2];
   double cube[6];  // root_kernel
-  int32_t bad;     // validate_kernel
+  int32_t bad;     // input check (bbox_kernel)
   int32_t ng, nw, leaves;
 };
 
@@ -878,15 +876,14 @@ int build_device_tree(const float* pos_in, const float* mass_in, bool inputs_on_
       return fail("input upload failed");
     pos = p;
     mass = q;
-  } else {
-    validate_kernel<<<std::min<int64_t>(2048, blocks(n)), kT, 0, s>>>(pos, mass, n, &info->bad);
   }
+  const bool check = inputs_on_device;  // then bbox_kernel checks them
 
   // Root cube (the host's rule on the device's bounding box).
   const int nbb = (int)std::min<int64_t>(1024, blocks(n));
   float* bbp = S.get<float>(6 * nbb);
   if (!bbp) return fail("device allocation failed");
-  bbox_kernel<<<nbb, kT, 0, s>>>(pos, n, bbp);
+  bbox_kernel<<<nbb, kT, 0, s>>>(pos, check ? mass : nullptr, n, bbp, &info->bad);
   root_kernel<<<1, kT, 0, s>>>(bbp, nbb, info->cube);
 
   // Keys and the stable sort (ties keep the input order).

@@ -67,6 +67,17 @@ def test_sim_argument_checks():
         og.Sim(pos, vel, m)
 
 
+def test_rebuild_rejects_positions_out_of_range():
+    # dt = 1e30 drifts the particles to |x| >= 2^60 (FP32 inf): the GPU
+    # rebuild's input check, done in its bounding-box pass over the
+    # device-resident positions, must refuse them
+    _torch()
+    pos, vel, m = W.plummer_with_velocities(2048, 15)
+    S = og.Sim(pos, vel, m)
+    with pytest.raises(og.OctgravError, match="finite"):
+        S.run(0.5, 0.01, 1e30, 2)
+
+
 def test_failed_step_leaves_the_handle_refusing(monkeypatch):
     """A rebuild that fails inside a step (injected allocation failure) marks
     the handle inconsistent: later runs, energies and states are refused.  A
