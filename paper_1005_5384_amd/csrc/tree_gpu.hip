@@ -482,8 +482,8 @@ __global__ void gather_kernel(const float4* __restrict__ packed, const int32_t* 
 __device__ __forceinline__ double hmin(double a, double b) { return b < a ? b : a; }
 __device__ __forceinline__ double hmax(double a, double b) { return a < b ? b : a; }
 
-// Boxes and FP64 moments of the cells [a, b) (one level), as the host does.
-// The loads of a leaf's particles (kMomChunk at a time) and of a cell's
+// Box and FP64 moments of one cell, as the host computes them.  The loads of
+// a leaf's particles (kMomChunk at a time) and of a cell's
 // children (four at a time) are issued before their sums, so a cell costs a
 // few memory round trips instead of one per particle or child.  The sums keep the
 // host's order; a slot past the end repeats the last particle or child with
